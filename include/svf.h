@@ -1,0 +1,191 @@
+/*
+ * svf.h -- C ABI of libsvf, a gfx950 (MI355X) implementation of O(1)-per-pixel
+ * space-variant elliptical filtering with the four-directional box spline of
+ * Chaudhury, Munoz-Barrutia and Unser, "Fast space-variant elliptical
+ * filtering using box splines".
+ *
+ * What is computed (per channel, per pass):
+ *
+ *     out[n] = sum_k f[k] beta^4_{a(n)}(n - k)            (eq. (discrete) with
+ *                                                          the Dirac-comb input)
+ *
+ * realised by Algorithm 1: the running sums RS1..RS4 with lattice scales
+ * b = (1, sqrt2, 1, sqrt2) (Sec. 4.1 step (1)), then at every pixel the 16-tap
+ * finite difference of eq. (final_eqn) with the taps of Table 1 and the shift
+ * tau of Sec. 4.1 step (2), sampling the ZP-interpolated pre-integrated image
+ * (App. F).  The per-pixel scale vector a(n) comes from the pixel's covariance
+ * by the optimisation of Sec. 4.2.2; order m > 1 runs m passes with a/sqrt(m)
+ * (Sec. 4.3).  N (directions) must be 4.
+ *
+ * Conventions (all entry points):
+ *  - Images are row-major: sample (row r, column c, channel ch) sits at
+ *    data[r * row_stride + c * channels + ch]; x = column, y = row; an
+ *    orientation theta is measured from +x towards +y.  Outside the image the
+ *    input is zero (zero extension).
+ *  - Every pointer to image, field or output data is DEVICE memory owned by the
+ *    caller; the library never frees it.  The library owns its workspace, which
+ *    lives in the context (allocated on first use, reused, grown on demand).
+ *  - Work is enqueued on the caller's stream and returns without waiting,
+ *    except where a report is requested (svf_filter with rep != NULL, the
+ *    batch and server calls documented below).
+ *  - No exception crosses the ABI.  Argument errors are detected on the host
+ *    before anything is enqueued and returned as a status; svf_last_error()
+ *    gives a message.  A context must not be used from two threads at once.
+ */
+#ifndef SVF_H
+#define SVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SVF_OK = 0,
+    SVF_EINVAL = 1,        /* bad argument, or (with a report) invalid field content */
+    SVF_EUNSUPPORTED = 2,  /* N != 4, unsupported dtype / variant combination */
+    SVF_ENOMEM = 3,        /* workspace would exceed the context's HBM budget, or allocation failed */
+    SVF_EHIP = 4,          /* a HIP runtime call failed */
+    SVF_EBUSY = 5,         /* server queue full / request not admitted */
+    SVF_ECANCELLED = 6,    /* request cancelled */
+    SVF_ERANGE = 7         /* (with a report) a support exceeded max_reach_px; those outputs are not valid */
+} svf_status;
+
+typedef enum { SVF_F32 = 0, SVF_U16 = 1 } svf_dtype;
+
+/* Per-pixel field describing the filter at each pixel (float32, H x W x K). */
+typedef enum {
+    SVF_FIELD_COV3 = 0,    /* K = 3: (C11, C12, C22) covariance of the whole filter, px^2 (descriptor D3) */
+    SVF_FIELD_SRT3 = 1,    /* K = 3: (sigma, rho, theta): size s = 2 sigma^2 = lambda_max + lambda_min,
+                              elongation rho = lambda_max / lambda_min >= 1, orientation theta (rad) of the
+                              major axis (descriptor D1; isotropic covariance sigma^2 I) */
+    SVF_FIELD_SCALES4 = 2  /* K = 4: box scales (a1, a2, a3, a4) of the whole filter, px (> 0);
+                              pass scales are a / sqrt(order) */
+} svf_field_kind;
+
+/* Arithmetic of the running sums. */
+typedef enum {
+    SVF_PRE_F64 = 0,   /* binary64 sums */
+    SVF_PRE_F32C = 1,  /* binary32 pairs (hi, lo) with error-free (two-sum / two-product) accumulation */
+    SVF_PRE_I64 = 2    /* exact 64-bit integer sums without the sqrt2 factors (uint16 input, first pass);
+                          later passes of an order > 1 filter use SVF_PRE_F64 */
+} svf_preint;
+
+typedef struct {
+    void *data;          /* device pointer */
+    int32_t dtype;       /* svf_dtype; outputs are always SVF_F32 */
+    int32_t channels;    /* 1..4 */
+    int64_t H, W;        /* rows, columns (>= 0) */
+    int64_t row_stride;  /* elements between rows, >= W * channels */
+} svf_image;
+
+typedef struct {
+    const float *data;   /* device pointer, H x W x K floats (K = 3 or 4) */
+    int32_t kind;        /* svf_field_kind */
+    int32_t reserved;
+    int64_t row_stride;  /* floats between rows, >= W * K; for SCALES4 a multiple of 4 (16-byte rows) */
+} svf_field;
+
+typedef struct {
+    int32_t preint;       /* svf_preint, default SVF_PRE_F64 */
+    int32_t fd_fp32;      /* 0: finite difference and interpolation in binary64 (default);
+                             1: in binary32 (comparison variant; far less accurate) */
+    double eps_px2;       /* floor on a_k^2 of every pass, px^2 (default 0.25, i.e. a_k >= 0.5 px);
+                             the solve of the whole filter uses order * eps_px2 */
+    int32_t tile;         /* output tile side for the segment-local pre-integration: 0 = automatic,
+                             else 64, 128 or 256 */
+    int32_t max_reach_px; /* largest support half-width of one pass the workspace is sized for
+                             (default 128 px; <= 380) */
+} svf_opts;
+
+typedef struct {
+    int64_t clamped_px;    /* pixels whose elongation was lowered to the feasible maximum */
+    int64_t eps_active_px; /* pixels with a component of a^2 at the floor */
+    int64_t invalid_px;    /* pixels with a non-finite / non-positive-definite field entry
+                              (filtered with the smallest isotropic scales instead) */
+    int64_t overflow_px;   /* pixels whose support exceeded max_reach_px */
+    double max_reach_px;   /* largest support half-width of one pass over the image */
+} svf_report;
+
+typedef struct svf_ctx svf_ctx;
+
+/* Fill opts with the defaults listed above. */
+void svf_default_opts(svf_opts *opts);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the workspace
+ * (0 = no cap).  Returns SVF_EHIP if the device cannot be selected. */
+svf_status svf_create(svf_ctx **ctx, int device, size_t hbm_budget_bytes);
+
+/* Release the workspace and the context.  Waits for the context's pending work. */
+svf_status svf_destroy(svf_ctx *ctx);
+
+/* Message of the last error on this context (never NULL). */
+const char *svf_last_error(const svf_ctx *ctx);
+
+/* Device workspace, in bytes, that svf_filter needs for these arguments
+ * (Sec. 4.1: one pre-integrated window per output tile and channel, sized by
+ * opts->max_reach_px; plus the scale field).  Host-only, no device access. */
+svf_status svf_workspace_bytes(const svf_image *in, int N, int order, const svf_opts *opts, size_t *bytes);
+
+/*
+ * Scale-vector map (Sec. 4.2.2, Prop. 4.1): field -> scales of the whole
+ * filter, float32 (a1, a2, a3, a4) per pixel into scales_out (device, H x W x 4,
+ * contiguous).  An infeasible elongation is lowered to the largest feasible one
+ * at the same size and orientation; eps is opts->eps_px2 * order.
+ */
+svf_status svf_scale_map(svf_ctx *ctx, const svf_field *field, int64_t H, int64_t W, int order,
+                         const svf_opts *opts, float *scales_out, hipStream_t stream);
+
+/*
+ * Running sums RS1..RS4 (Sec. 4.1 step (1), Algorithm 1 step 2) of channel
+ * `channel` of `in`, on the window rows [r0, r0+h) x cols [c0, c0+w) of the
+ * lattice (may extend beyond the image: the input is zero there), with zero
+ * initial conditions at the window's top, left and right edges.  g_out
+ * (device, h x w contiguous) receives:
+ *   SVF_PRE_F64  : double, g_b;
+ *   SVF_PRE_F32C : float pairs (hi, lo) with hi + lo = g_b;
+ *   SVF_PRE_I64  : int64, the integer sums G with g_b = 2 G (uint16 input only; exact).
+ * Window side limited to 1024 columns.
+ */
+svf_status svf_preintegrate(svf_ctx *ctx, const svf_image *in, int channel, int64_t r0, int64_t c0, int64_t h,
+                            int64_t w, int preint, void *g_out, hipStream_t stream);
+
+/*
+ * The filter: order-`order` (1..3) space-variant filtering of every channel of
+ * `in` with the field, N = 4.  out must be SVF_F32 with in's H, W, channels; it
+ * may be the same buffer as an SVF_F32 input.  If rep != NULL the call waits
+ * for completion, fills *rep, and returns SVF_EINVAL if invalid_px > 0 or
+ * SVF_ERANGE if overflow_px > 0.
+ */
+svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int N, int order,
+                      const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep);
+
+/*
+ * Many images in one launch sequence: n images, each with its own field and
+ * order (1..3).  All tiles of all images share one scale-map launch and, per
+ * pass, one pre-integration and one finite-difference launch over a device
+ * descriptor table (persistent work lists).  With use_graph != 0 the launch
+ * sequence is captured once per distinct shape set into a HIP graph and
+ * replayed.  Results are identical to n svf_filter calls.  Returns after
+ * enqueueing (the descriptor upload is stream-ordered).
+ */
+svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
+                            const svf_opts *opts, svf_image *out, hipStream_t stream, int use_graph);
+
+/* ---- kernel timing (for benchmarks): HIP events around every launch of the
+ * library's kernels on the caller's stream. ---- */
+svf_status svf_set_timing(svf_ctx *ctx, int enable);
+/* Sum of event-measured durations (ms) and launch count of one kernel class
+ * ("scale_map", "preint", "fd", "batch": a whole batch launch sequence) since the last reset; waits for the recorded
+ * events.  reset != 0 clears the accumulators afterwards. */
+svf_status svf_kernel_time(svf_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVF_H */

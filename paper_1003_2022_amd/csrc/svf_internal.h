@@ -1,0 +1,84 @@
+// svf_internal.h -- shared between the gfx950 kernels (svf_kernels.hip) and the
+// host runtime (svf_runtime.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svf {
+
+constexpr int kScanThreads = 256;    // one work-group per (tile, channel) window
+constexpr int kScanChunks = 4;       // window width <= 4 * 256 columns
+constexpr int kMaxWindow = kScanThreads * kScanChunks;
+constexpr int kFdBlockX = 64;        // finite-difference block: 64 columns x 4 rows
+constexpr int kFdBlockY = 4;
+constexpr int kMaxChannels = 4;
+
+enum Preint : int32_t { kPreF64 = 0, kPreF32C = 1, kPreI64 = 2 };
+enum InType : int32_t { kInF32 = 0, kInU16 = 1 };
+enum FieldKind : int32_t { kCov3 = 0, kSrt3 = 1, kScales4 = 2 };
+
+// Device counters filled by the scale map (order of the svf_report fields).
+enum Counter { kClamped = 0, kEpsActive = 1, kInvalid = 2, kOverflow = 3, kNumCounters = 4 };
+
+// One image of a filter call, for one pass.  Passed by value for a single image
+// and stored in a device table for batched launches.
+struct Job {
+    // pass input (pass 1: the caller's image; later passes: the output buffer)
+    const void *in;
+    int64_t in_rs;           // elements between rows
+    int32_t in_type;         // InType
+    int32_t C;               // channels (1..4)
+    int64_t H, W;
+    // output (float32, same layout rules)
+    float *out;
+    int64_t out_rs;
+    // scales of the whole filter, float4 per pixel
+    const float *scales;
+    int64_t sc_rs;           // floats between rows (multiple of 4)
+    // field (scale map input)
+    const float *field;
+    int64_t f_rs;
+    int32_t f_kind;
+    int32_t preint;          // Preint of this pass
+    // segment-local pre-integration
+    float *tile_reach;       // per tile: max support half-widths (x, y) of the whole filter
+    void *g;                 // window slots: (tile * C + ch) * slot_elems elements of the g type
+    int64_t slot_elems;
+    int32_t T;               // tile side
+    int32_t ntr, ntc;        // tile rows / columns
+    int32_t cap;             // largest half-width a window is sized for (one pass)
+    float inv_sqrt_m;        // 1 / sqrt(order)
+    int32_t fd_fp32;
+    double inv_sqrt_m_d;
+    double eps_full;         // floor on a^2 of the whole filter (order * eps per pass)
+    unsigned long long *counters;
+    // batched launches: first global tile / FD block / scale block of this job
+    int32_t tile_base, blk_base, smap_base, pad0;
+};
+
+// Rectangle of lattice samples pre-integrated for one tile.
+struct Window {
+    int64_t r0, c0;
+    int32_t h, w;
+};
+
+// Host-side launchers (defined in svf_kernels.hip).  All enqueue on `s`.
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_scale_map(const Job &j, hipStream_t s);
+hipError_t launch_preint(const Job &j, hipStream_t s);
+hipError_t launch_fd(const Job &j, hipStream_t s);
+// standalone pre-integration of a caller-given window (svf_preintegrate)
+hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c0, int h, int w, void *g,
+                                hipStream_t s);
+// batched: `jobs` is a device table of n jobs; totals are the sums of the per-job counts
+// (persistent: `grid` work-groups loop over the work list)
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, hipStream_t s);
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s);
+hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, hipStream_t s);
+
+int64_t slot_elems_for(int T, int cap);
+int scale_map_blocks(int64_t H, int64_t W);
+int fd_blocks_job(const Job &j);   // tile-major FD blocks, ragged edge tiles included
+
+}  // namespace svf

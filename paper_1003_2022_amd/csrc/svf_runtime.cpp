@@ -1,0 +1,462 @@
+// svf_runtime.cpp -- host side of libsvf: argument checks, tile planning,
+// workspace, launch sequences, kernel timing.  Implements include/svf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "svf.h"
+#include "svf_internal.h"
+#include "svf_runtime_internal.h"
+
+using namespace svf;
+
+namespace {
+
+constexpr int kDefaultCap = 128;
+constexpr double kDefaultEps = 0.25;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+const char *kClassNames[kNumKernelClasses] = {"scale_map", "preint", "fd", "batch"};
+
+}  // namespace
+
+namespace svf {
+
+svf_status fail(svf_ctx *ctx, svf_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+svf_status hip_fail(svf_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, SVF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+hipError_t timed_launch(svf_ctx *ctx, int cls, hipStream_t s, const std::function<hipError_t()> &fn)
+{
+    if (!ctx->timing) return fn();
+    hipEvent_t a = ctx->take_event(), b = ctx->take_event();
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    ctx->pending.push_back({cls, a, b});
+    return e;
+}
+
+int pick_tile(int64_t H, int64_t W, int requested)
+{
+    if (requested == 64 || requested == 128 || requested == 256) return requested;
+    auto tiles = [&](int64_t T) { return ((H + T - 1) / T) * ((W + T - 1) / T); };
+    if (tiles(256) >= 96) return 256;
+    if (tiles(128) >= 48) return 128;
+    return 64;
+}
+
+svf_status check_opts(svf_ctx *ctx, const svf_opts *o, int T)
+{
+    if (o->preint < 0 || o->preint > 2) return fail(ctx, SVF_EINVAL, "opts.preint must be 0..2");
+    if (!(o->eps_px2 > 0.0) || !std::isfinite(o->eps_px2)) return fail(ctx, SVF_EINVAL, "opts.eps_px2 must be > 0");
+    if (o->tile != 0 && o->tile != 64 && o->tile != 128 && o->tile != 256)
+        return fail(ctx, SVF_EINVAL, "opts.tile must be 0, 64, 128 or 256");
+    const int capmax = (kMaxWindow - T - 5) / 2;
+    if (o->max_reach_px < 1 || o->max_reach_px > capmax)
+        return fail(ctx, SVF_EINVAL, "opts.max_reach_px must be in [1, %d] for tile %d", capmax, T);
+    return SVF_OK;
+}
+
+svf_status check_image(svf_ctx *ctx, const svf_image *im, const char *what, bool output)
+{
+    if (!im) return fail(ctx, SVF_EINVAL, "%s is NULL", what);
+    if (im->H < 0 || im->W < 0) return fail(ctx, SVF_EINVAL, "%s: negative size", what);
+    if (im->H > (int64_t)1 << 20 || im->W > (int64_t)1 << 20) return fail(ctx, SVF_EINVAL, "%s: side above 2^20", what);
+    if (im->channels < 1 || im->channels > kMaxChannels) return fail(ctx, SVF_EINVAL, "%s: channels must be 1..4", what);
+    if (im->dtype != SVF_F32 && im->dtype != SVF_U16) return fail(ctx, SVF_EUNSUPPORTED, "%s: dtype", what);
+    if (output && im->dtype != SVF_F32) return fail(ctx, SVF_EUNSUPPORTED, "%s: output must be SVF_F32", what);
+    if (im->H > 0 && im->W > 0) {
+        if (!im->data) return fail(ctx, SVF_EINVAL, "%s: NULL data", what);
+        if (im->row_stride < im->W * im->channels) return fail(ctx, SVF_EINVAL, "%s: row_stride < W*channels", what);
+    }
+    return SVF_OK;
+}
+
+svf_status check_field(svf_ctx *ctx, const svf_field *f, int64_t H, int64_t W)
+{
+    if (!f) return fail(ctx, SVF_EINVAL, "field is NULL");
+    if (f->kind < 0 || f->kind > 2) return fail(ctx, SVF_EINVAL, "field.kind must be 0..2");
+    const int K = f->kind == SVF_FIELD_SCALES4 ? 4 : 3;
+    if (H > 0 && W > 0) {
+        if (!f->data) return fail(ctx, SVF_EINVAL, "field: NULL data");
+        if (f->row_stride < W * K) return fail(ctx, SVF_EINVAL, "field.row_stride < W*K");
+        if (K == 4 && (f->row_stride % 4 != 0 || (reinterpret_cast<uintptr_t>(f->data) & 15) != 0))
+            return fail(ctx, SVF_EINVAL, "SCALES4 field needs 16-byte aligned rows");
+    }
+    return SVF_OK;
+}
+
+Plan plan_for(const svf_image *in, int order, const svf_opts *o)
+{
+    Plan p;
+    p.T = pick_tile(in->H, in->W, o->tile);
+    p.cap = o->max_reach_px;
+    p.ntr = (int)((in->H + p.T - 1) / p.T);
+    p.ntc = (int)((in->W + p.T - 1) / p.T);
+    p.slot = slot_elems_for(p.T, p.cap);
+    p.off_counters = 0;
+    p.off_reach = 256;
+    p.off_scales = align_up(p.off_reach + (size_t)p.ntr * p.ntc * 2 * sizeof(float), 256);
+    p.off_g = align_up(p.off_scales + (size_t)in->H * in->W * 4 * sizeof(float), 256);
+    p.bytes = p.off_g + (size_t)p.ntr * p.ntc * in->channels * p.slot * 8;
+    (void)order;
+    return p;
+}
+
+svf_status ensure_workspace(svf_ctx *ctx, size_t bytes)
+{
+    if (ctx->budget && bytes > ctx->budget)
+        return fail(ctx, SVF_ENOMEM, "workspace of %zu bytes exceeds the HBM budget of %zu", bytes, ctx->budget);
+    if (bytes <= ctx->ws_bytes) return SVF_OK;
+    hipError_t e;
+    if (ctx->ws) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+        hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    e = hipMalloc(&ctx->ws, bytes);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        return fail(ctx, SVF_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    ctx->ws_bytes = bytes;
+    ctx->ws_generation++;
+    return SVF_OK;
+}
+
+// Fill the parts of a job common to every pass.
+Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
+             unsigned char *ws)
+{
+    Job j;
+    std::memset(&j, 0, sizeof j);
+    j.in = in->data;
+    j.in_rs = in->row_stride;
+    j.in_type = in->dtype == SVF_U16 ? kInU16 : kInF32;
+    j.C = in->channels;
+    j.H = in->H;
+    j.W = in->W;
+    j.field = field->data;
+    j.f_rs = field->row_stride;
+    j.f_kind = field->kind;
+    if (field->kind == SVF_FIELD_SCALES4) {
+        j.scales = field->data;
+        j.sc_rs = field->row_stride;
+    } else {
+        j.scales = reinterpret_cast<const float *>(ws + p.off_scales);
+        j.sc_rs = in->W * 4;
+    }
+    j.tile_reach = reinterpret_cast<float *>(ws + p.off_reach);
+    j.g = ws + p.off_g;
+    j.slot_elems = p.slot;
+    j.T = p.T;
+    j.ntr = p.ntr;
+    j.ntc = p.ntc;
+    j.cap = p.cap;
+    j.inv_sqrt_m = (float)(1.0 / std::sqrt((double)order));
+    j.inv_sqrt_m_d = 1.0 / std::sqrt((double)order);
+    j.fd_fp32 = o->fd_fp32 ? 1 : 0;
+    j.eps_full = o->eps_px2 * order;
+    j.counters = reinterpret_cast<unsigned long long *>(ws + p.off_counters);
+    j.preint = o->preint;
+    return j;
+}
+
+}  // namespace svf
+
+// ============================================================================
+// svf_ctx methods
+// ============================================================================
+
+hipEvent_t svf_ctx::take_event()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+void svf_default_opts(svf_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->preint = SVF_PRE_F64;
+    o->fd_fp32 = 0;
+    o->eps_px2 = kDefaultEps;
+    o->tile = 0;
+    o->max_reach_px = kDefaultCap;
+}
+
+svf_status svf_create(svf_ctx **out, int device, size_t hbm_budget_bytes)
+{
+    if (!out) return SVF_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SVF_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return SVF_EHIP;
+    svf_ctx *c = new (std::nothrow) svf_ctx();
+    if (!c) return SVF_ENOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    if (hipHostMalloc(&c->host_pinned, 1 << 20, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SVF_ENOMEM;
+    }
+    *out = c;
+    return SVF_OK;
+}
+
+svf_status svf_destroy(svf_ctx *ctx)
+{
+    if (!ctx) return SVF_EINVAL;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    svf_batch_release(ctx);
+    for (auto &p : ctx->pending) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->pool) hipEventDestroy(e);
+    if (ctx->ws) hipFree(ctx->ws);
+    if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
+    delete ctx;
+    return SVF_OK;
+}
+
+const char *svf_last_error(const svf_ctx *ctx)
+{
+    if (!ctx) return "NULL context";
+    return ctx->err.c_str();
+}
+
+svf_status svf_workspace_bytes(const svf_image *in, int N, int order, const svf_opts *opts, size_t *bytes)
+{
+    if (!in || !bytes) return SVF_EINVAL;
+    if (N != 4) return SVF_EUNSUPPORTED;
+    if (order < 1 || order > 3) return SVF_EINVAL;
+    svf_opts o;
+    if (opts) o = *opts; else svf_default_opts(&o);
+    // sizes only: the data pointer is not needed here
+    if (in->H < 0 || in->W < 0 || in->H > ((int64_t)1 << 20) || in->W > ((int64_t)1 << 20)) return SVF_EINVAL;
+    if (in->channels < 1 || in->channels > kMaxChannels) return SVF_EINVAL;
+    const int T = pick_tile(in->H, in->W, o.tile);
+    if (check_opts(nullptr, &o, T) != SVF_OK) return SVF_EINVAL;
+    *bytes = plan_for(in, order, &o).bytes;
+    return SVF_OK;
+}
+
+svf_status svf_scale_map(svf_ctx *ctx, const svf_field *field, int64_t H, int64_t W, int order, const svf_opts *opts,
+                         float *scales_out, hipStream_t stream)
+{
+    if (!ctx) return SVF_EINVAL;
+    ctx->err.clear();
+    if (order < 1 || order > 3) return fail(ctx, SVF_EINVAL, "order must be 1..3");
+    if (H < 0 || W < 0) return fail(ctx, SVF_EINVAL, "negative size");
+    svf_opts o;
+    if (opts) o = *opts; else svf_default_opts(&o);
+    svf_status st = check_field(ctx, field, H, W);
+    if (st) return st;
+    if (field->kind == SVF_FIELD_SCALES4) return fail(ctx, SVF_EINVAL, "field already holds scales");
+    if (H == 0 || W == 0) return SVF_OK;
+    if (!scales_out || (reinterpret_cast<uintptr_t>(scales_out) & 15)) return fail(ctx, SVF_EINVAL, "scales_out must be 16-byte aligned");
+    svf_image im{nullptr, SVF_F32, 1, H, W, W};
+    const int T = pick_tile(H, W, o.tile);
+    st = check_opts(ctx, &o, T);
+    if (st) return st;
+    Plan p = plan_for(&im, order, &o);
+    st = ensure_workspace(ctx, p.off_scales);
+    if (st) return st;
+    hipSetDevice(ctx->device);
+    unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
+    Job j = base_job(&im, field, order, &o, p, ws);
+    j.scales = scales_out;
+    j.sc_rs = W * 4;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(p.off_scales / 4), stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fill");
+    e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(j, stream); });
+    if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+    return SVF_OK;
+}
+
+svf_status svf_preintegrate(svf_ctx *ctx, const svf_image *in, int channel, int64_t r0, int64_t c0, int64_t h,
+                            int64_t w, int preint, void *g_out, hipStream_t stream)
+{
+    if (!ctx) return SVF_EINVAL;
+    ctx->err.clear();
+    svf_status st = check_image(ctx, in, "in", false);
+    if (st) return st;
+    if (channel < 0 || channel >= in->channels) return fail(ctx, SVF_EINVAL, "channel out of range");
+    if (h < 0 || w < 0 || w > kMaxWindow || h > ((int64_t)1 << 24)) return fail(ctx, SVF_EINVAL, "window size (w <= %d)", kMaxWindow);
+    if (preint < 0 || preint > 2) return fail(ctx, SVF_EINVAL, "preint must be 0..2");
+    if (preint == SVF_PRE_I64 && in->dtype != SVF_U16) return fail(ctx, SVF_EUNSUPPORTED, "integer sums need a uint16 image");
+    if (h == 0 || w == 0) return SVF_OK;
+    if (!g_out) return fail(ctx, SVF_EINVAL, "g_out is NULL");
+    hipSetDevice(ctx->device);
+    Job j;
+    std::memset(&j, 0, sizeof j);
+    j.in = in->data;
+    j.in_rs = in->row_stride;
+    j.in_type = in->dtype == SVF_U16 ? kInU16 : kInF32;
+    j.C = in->channels;
+    j.H = in->H;
+    j.W = in->W;
+    j.preint = preint;
+    hipError_t e = timed_launch(ctx, kClsPreint, stream,
+                                [&] { return launch_preint_window(j, channel, r0, c0, (int)h, (int)w, g_out, stream); });
+    if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
+    return SVF_OK;
+}
+
+svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int N, int order, const svf_opts *opts,
+                      svf_image *out, hipStream_t stream, svf_report *rep)
+{
+    if (!ctx) return SVF_EINVAL;
+    ctx->err.clear();
+    if (N != 4) return fail(ctx, SVF_EUNSUPPORTED, "only N = 4 directions (ZP lattice) is supported");
+    if (order < 1 || order > 3) return fail(ctx, SVF_EINVAL, "order must be 1..3");
+    svf_opts o;
+    if (opts) o = *opts; else svf_default_opts(&o);
+    svf_status st = check_image(ctx, in, "in", false);
+    if (st) return st;
+    st = check_image(ctx, out, "out", true);
+    if (st) return st;
+    if (out->H != in->H || out->W != in->W || out->channels != in->channels)
+        return fail(ctx, SVF_EINVAL, "out must have the input's H, W and channels");
+    st = check_field(ctx, field, in->H, in->W);
+    if (st) return st;
+    const int T = pick_tile(in->H, in->W, o.tile);
+    st = check_opts(ctx, &o, T);
+    if (st) return st;
+    if (o.preint == SVF_PRE_I64 && in->dtype != SVF_U16)
+        return fail(ctx, SVF_EUNSUPPORTED, "integer pre-integration needs a uint16 image");
+    if (rep) std::memset(rep, 0, sizeof *rep);
+    if (in->H == 0 || in->W == 0) return SVF_OK;
+    Plan p = plan_for(in, order, &o);
+    st = ensure_workspace(ctx, p.bytes);
+    if (st) return st;
+    hipSetDevice(ctx->device);
+    unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
+    Job j = base_job(in, field, order, &o, p, ws);
+    j.out = static_cast<float *>(out->data);
+    j.out_rs = out->row_stride;
+
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(p.off_scales / 4), stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fill");
+    e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(j, stream); });
+    if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+    for (int pass = 0; pass < order; ++pass) {
+        Job jp = j;
+        if (pass > 0) {   // later passes read the previous output (float32), in place
+            jp.in = out->data;
+            jp.in_rs = out->row_stride;
+            jp.in_type = kInF32;
+            if (jp.preint == kPreI64) jp.preint = kPreF64;
+        }
+        e = timed_launch(ctx, kClsPreint, stream, [&] { return launch_preint(jp, stream); });
+        if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
+        e = timed_launch(ctx, kClsFd, stream, [&] { return launch_fd(jp, stream); });
+        if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
+    }
+    if (rep) {
+        const size_t nreach = (size_t)p.ntr * p.ntc * 2;
+        if (32 + nreach * 4 <= (1u << 20)) {
+            e = hipMemcpyAsync(ctx->host_pinned, ws, 32, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(static_cast<char *>(ctx->host_pinned) + 32, ws + p.off_reach, nreach * 4,
+                                   hipMemcpyDeviceToHost, stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "report");
+        const unsigned long long *cn = static_cast<const unsigned long long *>(ctx->host_pinned);
+        rep->clamped_px = (int64_t)cn[kClamped];
+        rep->eps_active_px = (int64_t)cn[kEpsActive];
+        rep->invalid_px = (int64_t)cn[kInvalid];
+        rep->overflow_px = (int64_t)cn[kOverflow];
+        const float *rr = reinterpret_cast<const float *>(static_cast<const char *>(ctx->host_pinned) + 32);
+        float mx = 0.f;
+        if (32 + nreach * 4 <= (1u << 20))
+            for (size_t i = 0; i < nreach; ++i) mx = std::max(mx, rr[i]);
+        rep->max_reach_px = mx / std::sqrt((double)order);
+        if (rep->invalid_px > 0) return fail(ctx, SVF_EINVAL, "%lld pixels with an invalid field entry", (long long)rep->invalid_px);
+        if (rep->overflow_px > 0)
+            return fail(ctx, SVF_ERANGE, "%lld pixels exceed max_reach_px = %d", (long long)rep->overflow_px, o.max_reach_px);
+    }
+    return SVF_OK;
+}
+
+svf_status svf_set_timing(svf_ctx *ctx, int enable)
+{
+    if (!ctx) return SVF_EINVAL;
+    ctx->timing = enable != 0;
+    return SVF_OK;
+}
+
+svf_status svf_kernel_time(svf_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int reset)
+{
+    if (!ctx || !kernel) return SVF_EINVAL;
+    int cls = -1;
+    for (int i = 0; i < kNumKernelClasses; ++i)
+        if (std::strcmp(kernel, kClassNames[i]) == 0) cls = i;
+    if (cls < 0) return fail(ctx, SVF_EINVAL, "unknown kernel class %s", kernel);
+    // fold every finished record into the accumulators
+    std::vector<svf_ctx::Rec> keep;
+    for (auto &r : ctx->pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+        ctx->tot_ms[r.cls] += ms;
+        ctx->count[r.cls] += 1;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->pending.clear();
+    if (total_ms) *total_ms = ctx->tot_ms[cls];
+    if (launches) *launches = ctx->count[cls];
+    if (reset) {
+        for (int i = 0; i < kNumKernelClasses; ++i) {
+            ctx->tot_ms[i] = 0.0;
+            ctx->count[i] = 0;
+        }
+    }
+    return SVF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// svf_runtime_internal.h -- host-side state shared by the runtime files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "svf.h"
+#include "svf_internal.h"
+
+enum { kClsScaleMap = 0, kClsPreint = 1, kClsFd = 2, kClsBatch = 3, kNumKernelClasses = 4 };
+
+struct svf_ctx {
+    int device = 0;
+    size_t budget = 0;                 // cap on the workspace (0 = none)
+    void *ws = nullptr;                // device workspace (grown on demand)
+    size_t ws_bytes = 0;
+    uint64_t ws_generation = 0;        // bumped when the workspace moves (invalidates graphs)
+    void *host_pinned = nullptr;       // 1 MiB of pinned host memory for reports / descriptors
+    std::string err;
+    bool timing = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double tot_ms[kNumKernelClasses] = {};
+    int64_t count[kNumKernelClasses] = {};
+    void *batch = nullptr;             // svf::BatchState
+    hipEvent_t take_event();
+};
+
+namespace svf {
+
+struct Plan {
+    int T = 0, cap = 0, ntr = 0, ntc = 0;
+    int64_t slot = 0;
+    size_t off_counters = 0, off_reach = 0, off_scales = 0, off_g = 0, bytes = 0;
+};
+
+svf_status fail(svf_ctx *ctx, svf_status st, const char *fmt, ...);
+svf_status hip_fail(svf_ctx *ctx, hipError_t e, const char *what);
+hipError_t timed_launch(svf_ctx *ctx, int cls, hipStream_t s, const std::function<hipError_t()> &fn);
+int pick_tile(int64_t H, int64_t W, int requested);
+svf_status check_opts(svf_ctx *ctx, const svf_opts *o, int T);
+svf_status check_image(svf_ctx *ctx, const svf_image *im, const char *what, bool output);
+svf_status check_field(svf_ctx *ctx, const svf_field *f, int64_t H, int64_t W);
+Plan plan_for(const svf_image *in, int order, const svf_opts *o);
+svf_status ensure_workspace(svf_ctx *ctx, size_t bytes);
+Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
+             unsigned char *ws);
+
+}  // namespace svf
+
+void svf_batch_release(svf_ctx *ctx);

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerance for float outputs (FP64 pre-integration and finite difference):
+per pixel |gpu - ref| <= 1e-5 * max(|ref|, 1e-3 * max|ref|) and RMS relative
+<= 1e-6.  The integer pre-integration must be bit-exact.
+"""
+import numpy as np
+import pytest
+
+from paper_1003_2022_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _has_gpu():
+    return torch.cuda.is_available()
+
+
+if not _has_gpu():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1003_2022_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def check_close(got, ref, tol=1e-5, rms_tol=1e-6, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape
+    assert np.isfinite(got).all(), f"{what}: non-finite output"
+    scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    rel = np.abs(got - ref) / scale
+    rms = np.sqrt(np.mean(((got - ref) / scale) ** 2))
+    print(f"{what}: max rel {rel.max():.3e}  rms rel {rms:.3e}", flush=True)
+    assert rel.max() <= tol, f"{what}: max rel err {rel.max():.3e} at {np.unravel_index(rel.argmax(), rel.shape)}"
+    assert rms <= rms_tol, f"{what}: rms rel err {rms:.3e}"
+    return rel.max(), rms
+
+
+def gpu_filter(ctx, img, fld, kind, order, **opts):
+    out, st, rep = P.filter_tensor(ctx, to_dev(img), to_dev(fld), kind, order=order, report=True, **opts)
+    torch.cuda.synchronize()
+    assert st == P.SVF_OK, ctx.last_error()
+    return out.cpu().numpy(), rep
+
+
+# ----------------------------------------------------------------------------- running sums
+
+@pytest.mark.parametrize("win", [(-5, -7, 90, 130), (0, 0, 64, 64), (40, 250, 70, 300), (-3, 290, 40, 60)])
+def test_preint_i64_bit_exact(ctx, win):
+    img = I.uniform_image(120, 333, 3001, "u16")
+    r0, c0, h, w = win
+    g = torch.empty((h, w), dtype=torch.int64, device=DEV)
+    P.svf_preintegrate(ctx, P.image_of(to_dev(img)), 0, r0, c0, h, w, P.SVF_PRE_I64, g)
+    torch.cuda.synchronize()
+    ref = oracle.preint_window_i64(img, r0, c0, h, w)
+    assert np.array_equal(g.cpu().numpy(), ref)
+
+
+def test_preint_i64_bit_exact_large_wrapping(ctx):
+    # full 4096-row windows of a 4096 x 4096 uint16 image: magnitudes beyond 2^63 wrap identically
+    img = I.uniform_image(4096, 4096, 3003, "u16")
+    timg = to_dev(img)
+    for (r0, c0, h, w) in [(-6, -5, 4110, 1024), (-6, 3085, 4110, 1024)]:
+        g = torch.empty((h, w), dtype=torch.int64, device=DEV)
+        P.svf_preintegrate(ctx, P.image_of(timg), 0, r0, c0, h, w, P.SVF_PRE_I64, g)
+        torch.cuda.synchronize()
+        ref = oracle.preint_window_i64(img, r0, c0, h, w)
+        assert np.array_equal(g.cpu().numpy(), ref), (r0, c0)
+
+
+def test_preint_f64_and_f32c(ctx):
+    img = I.uniform_image(150, 200, 3002)
+    r0, c0, h, w = -4, -6, 170, 230
+    ref = oracle.preint_window_f64(img, r0, c0, h, w)
+    g = torch.empty((h, w), dtype=torch.float64, device=DEV)
+    P.svf_preintegrate(ctx, P.image_of(to_dev(img)), 0, r0, c0, h, w, P.SVF_PRE_F64, g)
+    g2 = torch.empty((h, w, 2), dtype=torch.float32, device=DEV)
+    P.svf_preintegrate(ctx, P.image_of(to_dev(img)), 0, r0, c0, h, w, P.SVF_PRE_F32C, g2)
+    torch.cuda.synchronize()
+    e64 = np.abs(g.cpu().numpy() - ref).max() / np.abs(ref).max()
+    pair = g2.cpu().numpy().astype(np.float64)
+    e32 = np.abs(pair[..., 0] + pair[..., 1] - ref).max() / np.abs(ref).max()
+    print(f"preint rel err: f64 {e64:.2e}  f32c {e32:.2e}")
+    assert e64 < 1e-14
+    assert e32 < 1e-11
+
+
+# ----------------------------------------------------------------------------- scale map
+
+@pytest.mark.parametrize("kind", [P.SVF_FIELD_SRT3, P.SVF_FIELD_COV3])
+def test_scale_map(ctx, kind):
+    H, W = 70, 90
+    fld = I.srt_field(H, W, 3010, (0.3, 32.0), (1.0, 7.0), corr_len=6.0)
+    if kind == P.SVF_FIELD_COV3:
+        s = 2 * fld[..., 0].astype(np.float64) ** 2
+        rho, th = fld[..., 1].astype(np.float64), fld[..., 2].astype(np.float64)
+        lmax, lmin = s * rho / (1 + rho), s / (1 + rho)
+        c, sn = np.cos(th), np.sin(th)
+        fld = np.stack([lmax * c * c + lmin * sn * sn, (lmax - lmin) * c * sn, lmin * c * c + lmax * sn * sn], -1).astype(np.float32)
+    for order in (1, 2, 3):
+        sc = torch.empty((H, W, 4), dtype=torch.float32, device=DEV)
+        P.svf_scale_map(ctx, P.field_of(to_dev(fld), kind), H, W, order, None, sc)
+        torch.cuda.synchronize()
+        ref, stats = oracle.scales(fld, kind, order)
+        got = sc.cpu().numpy().astype(np.float64) / np.sqrt(order)   # per-pass scales
+        rel = np.abs(got - ref) / ref
+        print(f"kind {kind} order {order}: max rel {rel.max():.2e}, clamped {stats['clamped']}")
+        assert rel.max() < 3e-7
+
+
+# ----------------------------------------------------------------------------- whole filter, small sizes
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_filter_64_srt(ctx, order):
+    # 64 x 64, sigma in [1,4], elongation in [1,3], seeded smooth field
+    img = I.uniform_image(64, 64, 1000)
+    fld = I.srt_field(64, 64, 1000, (1.0, 4.0), (1.0, 3.0))
+    got, rep = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, order)
+    ref = oracle.filter(img, fld, oracle.FIELD_SRT3, order)
+    check_close(got, ref, what=f"64x64 order {order}")
+    if order == 1:
+        brute = oracle.filter(img, fld, oracle.FIELD_SRT3, order, method="brute")
+        check_close(got, brute, what="64x64 vs direct sum")
+
+
+@pytest.mark.parametrize("shape,tile", [((200, 333), 64), ((131, 67), 64), ((300, 257), 128), ((5, 3), 64), ((1, 1), 64)])
+def test_filter_ragged_tiles(ctx, shape, tile):
+    H, W = shape
+    img = I.uniform_image(H, W, 3020 + H)
+    fld = I.srt_field(H, W, 3020 + H, (1.0, 6.0), (1.0, 6.0), corr_len=max(4.0, min(H, W) / 4))
+    got, rep = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, 2, tile=tile)
+    ref = oracle.filter(img, fld, oracle.FIELD_SRT3, 2)
+    check_close(got, ref, what=f"{H}x{W} tile {tile}")
+
+
+def test_filter_white_scales_and_multichannel(ctx):
+    H, W = 97, 141
+    img = I.uniform_image(H, W, 3030, channels=3)
+    sc = I.scales_field(H, W, 3030, 0.5, 6.0)
+    got, _ = gpu_filter(ctx, img, sc, P.SVF_FIELD_SCALES4, 1, tile=64)
+    ref = oracle.filter(img, sc, oracle.FIELD_SCALES4, 1)
+    check_close(got, ref, what="white scales 3ch")
+    got2, _ = gpu_filter(ctx, img, sc, P.SVF_FIELD_SCALES4, 2, tile=64)
+    ref2 = oracle.filter(img, sc, oracle.FIELD_SCALES4, 2)
+    check_close(got2, ref2, what="white scales 3ch order 2")
+
+
+def test_filter_uint16_integer_preint(ctx):
+    H, W = 150, 170
+    img = I.uniform_image(H, W, 3040, "u16")
+    fld = I.srt_field(H, W, 3040, (1.0, 8.0), (1.0, 6.0), corr_len=20.0)
+    for order in (1, 2):
+        got, _ = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, order, preint=P.SVF_PRE_I64, tile=64)
+        ref = oracle.filter(img, fld, oracle.FIELD_SRT3, order)
+        check_close(got, ref, what=f"u16 i64 order {order}")
+
+
+def test_filter_variants_report_error(ctx):
+    H, W = 180, 190
+    img = I.uniform_image(H, W, 3050)
+    fld = I.srt_field(H, W, 3050, (1.0, 16.0), (1.0, 4.0), corr_len=30.0)
+    ref = oracle.filter(img, fld, oracle.FIELD_SRT3, 2)
+    got, _ = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, 2, preint=P.SVF_PRE_F32C, tile=64)
+    check_close(got, ref, what="f32c", tol=1e-4, rms_tol=1e-5)
+    got32, _ = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, 2, fd_fp32=1, tile=64)
+    err = np.abs(got32 - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    print(f"fd fp32: max rel {err.max():.3e}  rms {np.sqrt(np.mean(err**2)):.3e}")
+    assert np.isfinite(got32).all()
+
+
+def test_constant_image_unit_mass_case(ctx):
+    # a1, a3 integers: the sampled kernel has unit mass, a constant image stays constant inside
+    H, W = 80, 80
+    img = np.full((H, W), 0.75, dtype=np.float32)
+    sc = np.broadcast_to(np.array([3.0, 2.2, 2.0, 1.7], np.float32), (H, W, 4)).copy()
+    got, _ = gpu_filter(ctx, img, sc, P.SVF_FIELD_SCALES4, 1)
+    np.testing.assert_allclose(got[10:-10, 10:-10], 0.75, rtol=1e-6)
+
+
+# ----------------------------------------------------------------------------- argument errors
+
+def test_errors(ctx):
+    img = to_dev(I.uniform_image(16, 16, 1))
+    fld = to_dev(I.srt_field(16, 16, 1))
+    out = torch.empty_like(img)
+    o = P.default_opts()
+    for N, order, exp in [(3, 1, P.SVF_EUNSUPPORTED), (4, 0, P.SVF_EINVAL), (4, 4, P.SVF_EINVAL)]:
+        with pytest.raises(P.SvfError) as ei:
+            P.svf_filter(ctx, P.image_of(img), P.field_of(fld, P.SVF_FIELD_SRT3), N, order, o, P.image_of(out))
+        assert ei.value.status == exp
+    # NaN in the field: reported, output still finite (smallest isotropic filter there)
+    bad = I.srt_field(16, 16, 1)
+    bad[3, 4, 0] = np.nan
+    out2, st, rep = P.filter_tensor(ctx, img, to_dev(bad), P.SVF_FIELD_SRT3, 1, report=True)
+    assert st == P.SVF_EINVAL and rep.invalid_px == 1
+    assert torch.isfinite(out2).all()
+    # empty image is a no-op
+    e = torch.empty((0, 7), dtype=torch.float32, device=DEV)
+    ef = torch.empty((0, 7, 3), dtype=torch.float32, device=DEV)
+    P.svf_filter(ctx, P.image_of(e), P.field_of(ef, P.SVF_FIELD_SRT3), 4, 1, o, P.image_of(e))
