@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
+    ap.add_argument("--tile", type=int, default=0, help="output tile side (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the filter's multi-GPU sharding "
@@ -102,7 +103,7 @@ def main():
     to = torch.empty_like(ti)
     ctx = P.Context(0)
     preint = P.SVF_PRE_F64 if args.preint == "f64" else P.SVF_PRE_F32C
-    o = P.default_opts(preint=preint)
+    o = P.default_opts(preint=preint, tile=args.tile)
     im_d, fl_d, out_d = P.image_of(ti), P.field_of(tf, P.SVF_FIELD_SRT3), P.image_of(to)
     stream = torch.cuda.current_stream()
 
@@ -171,6 +172,7 @@ def main():
             "image": [H, W],
             "order": ORDER,
             "preint": args.preint,
+            "tile": args.tile or "auto",
         },
         "roofline": roofline,
         **extra,

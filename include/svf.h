@@ -176,6 +176,64 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
 svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
                             const svf_opts *opts, svf_image *out, hipStream_t stream, int use_graph);
 
+/* ---- serving loop ----
+ * A scheduler thread owned by the context admits requests (images of any size,
+ * each with its own field and order) in arrival order while they fit in a
+ * device-memory budget and a slot limit, and runs them with continuous
+ * batching: every scheduler step enqueues, on the server's own stream, the
+ * scale map of the requests admitted since the last step and then ONE pass
+ * (pre-integration + finite difference) of every request in flight, all
+ * through the batched persistent kernels.  Requests join and leave between
+ * steps.  Each request computes exactly what svf_filter computes with the same
+ * options (opts.tile 0 means 256 here), so its result does not depend on the
+ * mix it ran in.  Input, field and output stay in caller-owned device memory
+ * that must remain valid until the request is done.  The integer
+ * pre-integration is not offered by the server (opts.preint must be F64 or
+ * F32C).
+ */
+typedef struct {
+    int32_t max_inflight;       /* requests on the device at once (default 16) */
+    int32_t queue_capacity;     /* waiting requests; submit returns SVF_EBUSY beyond (default 1024) */
+    uint64_t hbm_budget_bytes;  /* device memory for the windows and scales of requests in flight */
+    int32_t reserved0;
+    int32_t reserved1;
+    svf_opts opts;              /* options of every request */
+} svf_server_cfg;
+
+typedef struct {
+    svf_image in;
+    svf_field field;
+    int32_t order;
+    int32_t reserved;
+    svf_image out;
+} svf_request;
+
+typedef struct {
+    int32_t status;             /* SVF_OK when done, SVF_EBUSY while queued or running, else the error */
+    int32_t done;
+    double t_submit_us;         /* host steady clock, microseconds */
+    double t_admit_us;
+    double t_done_us;           /* when the host observed the request's last step complete */
+} svf_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, steps;
+    int64_t pixels;             /* output pixels x channels of completed requests */
+    double busy_us;             /* wall time with at least one request in flight */
+} svf_server_stats_t;
+
+/* Start the scheduler (allocates hbm_budget_bytes on the context's device). */
+svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg);
+/* Queue a request (arguments are checked here); *id identifies it. */
+svf_status svf_server_submit(svf_ctx *ctx, const svf_request *req, uint64_t *id);
+/* Non-blocking state of a request. */
+svf_status svf_server_poll(svf_ctx *ctx, uint64_t id, svf_result *res);
+/* Wait up to timeout_s seconds (< 0: forever) for a request; SVF_EBUSY on timeout. */
+svf_status svf_server_wait(svf_ctx *ctx, uint64_t id, svf_result *res, double timeout_s);
+svf_status svf_server_stats(svf_ctx *ctx, svf_server_stats_t *stats);
+/* Drain the queue, stop the thread, release the server's memory. */
+svf_status svf_server_stop(svf_ctx *ctx);
+
 /* ---- kernel timing (for benchmarks): HIP events around every launch of the
  * library's kernels on the caller's stream. ---- */
 svf_status svf_set_timing(svf_ctx *ctx, int enable);

@@ -26,6 +26,7 @@ namespace {
 constexpr int kPersistentScale = 4096;
 constexpr int kPersistentPreint = 2048;
 constexpr int kPersistentFd = 16384;
+constexpr int kTables = 1 + 3 * kMaxChannels;   // scale map + (pass, channel count)
 
 struct GraphEntry {
     std::string key;
@@ -34,7 +35,7 @@ struct GraphEntry {
 };
 
 struct BatchState {
-    Job *d_jobs = nullptr;        // 3 tables of up to `cap` jobs (one per pass)
+    Job *d_jobs = nullptr;        // kTables tables of up to `cap` jobs
     int cap = 0;
     Job *h_jobs = nullptr;        // pinned staging for the tables
     hipEvent_t upload_done = nullptr;
@@ -107,12 +108,12 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         plans[i] = plan_for(&in[i], orders[i], &oi);
         max_order = std::max(max_order, orders[i]);
     }
-    // ---- workspace: [counters+reach of all images][scales][g] ----
+    // ---- workspace: [tile stats of all images][scales][windows] ----
     std::vector<size_t> off_fill(n), off_scales(n), off_g(n);
     size_t pos = 0;
     for (int i = 0; i < n; ++i) {
         off_fill[i] = pos;
-        pos = align_up(pos + 256 + (size_t)plans[i].ntr * plans[i].ntc * 2 * sizeof(float), 256);
+        pos = align_up(pos + (size_t)plans[i].ntr * plans[i].ntc * sizeof(TileStat), 256);
     }
     const size_t fill_bytes = pos;
     for (int i = 0; i < n; ++i) {
@@ -141,9 +142,9 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         B->h_jobs = nullptr;
         B->cap = 0;
         const int cap = std::max(n, 64);
-        hipError_t e = hipMalloc(&B->d_jobs, sizeof(Job) * 3 * cap);
+        hipError_t e = hipMalloc(&B->d_jobs, sizeof(Job) * kTables * cap);
         if (e != hipSuccess) return fail(ctx, SVF_ENOMEM, "descriptor table: %s", hipGetErrorString(e));
-        e = hipHostMalloc(&B->h_jobs, sizeof(Job) * 3 * cap, hipHostMallocDefault);
+        e = hipHostMalloc(&B->h_jobs, sizeof(Job) * kTables * cap, hipHostMallocDefault);
         if (e != hipSuccess) return fail(ctx, SVF_ENOMEM, "descriptor staging: %s", hipGetErrorString(e));
         if (!B->upload_done) hipEventCreateWithFlags(&B->upload_done, hipEventDisableTiming);
         B->cap = cap;
@@ -153,26 +154,31 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         if (e != hipSuccess) return hip_fail(ctx, e, "descriptor upload");
         B->upload_pending = false;
     }
-    // ---- descriptor tables: table p holds the images with order > p ----
+    // ---- descriptor tables ----
+    // table 0: every image (scale map); table 1 + pass * kMaxChannels + (C - 1): the images
+    // with `channels` = C whose order exceeds `pass` (pre-integration and finite difference)
     unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
-    int counts[3] = {0, 0, 0};
-    int tot_smap = 0, tot_tiles[3] = {0, 0, 0}, tot_blk[3] = {0, 0, 0};
-    int preint_of_pass[3] = {o.preint, o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint,
-                             o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint};
+    int counts[kTables] = {};
+    int tot_smap = 0, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
+    const int preint_of_pass[3] = {o.preint, o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint,
+                                   o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint};
     std::string key = "n" + std::to_string(n);
+    int kc = 1;
     for (int i = 0; i < n; ++i) {
         Plan p = plans[i];
-        p.off_counters = off_fill[i];
-        p.off_reach = off_fill[i] + 256;
+        p.off_tstat = off_fill[i];
         p.off_scales = off_scales[i];
         p.off_g = off_g[i];
+        kc = std::max(kc, chunks_for(p.T, p.cap));
         svf_opts oi = o;
         Job base = base_job(&in[i], &fields[i], orders[i], &oi, p, ws);
         base.out = static_cast<float *>(out[i].data);
         base.out_rs = out[i].row_stride;
         base.smap_base = tot_smap;
         tot_smap += scale_map_blocks(in[i].H, in[i].W);
+        B->h_jobs[counts[0]++] = base;
         for (int pass = 0; pass < orders[i]; ++pass) {
+            const int tb = 1 + pass * kMaxChannels + (in[i].channels - 1);
             Job jp = base;
             jp.preint = preint_of_pass[pass];
             if (pass > 0) {
@@ -180,11 +186,11 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
                 jp.in_rs = out[i].row_stride;
                 jp.in_type = kInF32;
             }
-            jp.tile_base = tot_tiles[pass];
-            jp.blk_base = tot_blk[pass];
-            tot_tiles[pass] += p.ntr * p.ntc * in[i].channels;
-            tot_blk[pass] += fd_blocks_job(jp);
-            B->h_jobs[pass * B->cap + counts[pass]++] = jp;
+            jp.tile_base = tot_tiles[tb];
+            jp.blk_base = tot_blk[tb];
+            tot_tiles[tb] += p.ntr * p.ntc * in[i].channels;
+            tot_blk[tb] += fd_blocks_job(jp);
+            B->h_jobs[tb * B->cap + counts[tb]++] = jp;
         }
         char buf[160];
         snprintf(buf, sizeof buf, "|%lld,%lld,%d,%d,%d,%d,%d,%d", (long long)in[i].H, (long long)in[i].W,
@@ -196,7 +202,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         snprintf(buf, sizeof buf, "#%d,%d,%.17g", o.preint, o.fd_fp32, o.eps_px2);
         key += buf;
     }
-    hipError_t e = hipMemcpyAsync(B->d_jobs, B->h_jobs, sizeof(Job) * 3 * B->cap, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(B->d_jobs, B->h_jobs, sizeof(Job) * kTables * B->cap, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor upload");
     e = hipEventRecord(B->upload_done, stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor upload event");
@@ -208,11 +214,20 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         r = launch_scale_map_batch(B->d_jobs, counts[0], tot_smap, kPersistentScale, s);
         if (r != hipSuccess) return r;
         for (int pass = 0; pass < max_order; ++pass) {
-            const Job *tab = B->d_jobs + pass * B->cap;
-            r = launch_preint_batch(tab, counts[pass], tot_tiles[pass], kPersistentPreint, preint_of_pass[pass], s);
-            if (r != hipSuccess) return r;
-            r = launch_fd_batch(tab, counts[pass], tot_blk[pass], kPersistentFd, preint_of_pass[pass], o.fd_fp32, s);
-            if (r != hipSuccess) return r;
+            for (int ch = 1; ch <= kMaxChannels; ++ch) {
+                const int tb = 1 + pass * kMaxChannels + (ch - 1);
+                if (counts[tb] == 0) continue;
+                const Job *tab = B->d_jobs + tb * B->cap;
+                r = launch_preint_batch(tab, counts[tb], tot_tiles[tb], kPersistentPreint, preint_of_pass[pass], kc, s);
+                if (r != hipSuccess) return r;
+            }
+            for (int ch = 1; ch <= kMaxChannels; ++ch) {
+                const int tb = 1 + pass * kMaxChannels + (ch - 1);
+                if (counts[tb] == 0) continue;
+                const Job *tab = B->d_jobs + tb * B->cap;
+                r = launch_fd_batch(tab, counts[tb], tot_blk[tb], kPersistentFd, preint_of_pass[pass], o.fd_fp32, ch, s);
+                if (r != hipSuccess) return r;
+            }
         }
         return hipSuccess;
     };

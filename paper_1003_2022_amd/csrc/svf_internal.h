@@ -10,16 +10,22 @@ namespace svf {
 constexpr int kScanThreads = 256;    // one work-group per (tile, channel) window
 constexpr int kScanChunks = 4;       // window width <= 4 * 256 columns
 constexpr int kMaxWindow = kScanThreads * kScanChunks;
-constexpr int kFdBlockX = 64;        // finite-difference block: 64 columns x 4 rows
-constexpr int kFdBlockY = 4;
+constexpr int kSmapRows = 4;         // scale map: each thread handles 4 rows of a 64 x 16 block
+constexpr int kSmapCols = 64;        // scale map: block of 64 columns x 16 rows
 constexpr int kMaxChannels = 4;
 
 enum Preint : int32_t { kPreF64 = 0, kPreF32C = 1, kPreI64 = 2 };
 enum InType : int32_t { kInF32 = 0, kInU16 = 1 };
 enum FieldKind : int32_t { kCov3 = 0, kSrt3 = 1, kScales4 = 2 };
 
-// Device counters filled by the scale map (order of the svf_report fields).
-enum Counter { kClamped = 0, kEpsActive = 1, kInvalid = 2, kOverflow = 3, kNumCounters = 4 };
+// Per-tile results of the scale map: largest support half-widths of the whole
+// filter (sizing the tile's pre-integration window) and pixel counts for the report.
+struct TileStat {
+    float rx, ry;
+    uint32_t clamped, eps_active, invalid, overflow;
+    uint32_t pad0, pad1;
+};
+static_assert(sizeof(TileStat) == 32, "TileStat layout");
 
 // One image of a filter call, for one pass.  Passed by value for a single image
 // and stored in a device table for batched launches.
@@ -42,7 +48,7 @@ struct Job {
     int32_t f_kind;
     int32_t preint;          // Preint of this pass
     // segment-local pre-integration
-    float *tile_reach;       // per tile: max support half-widths (x, y) of the whole filter
+    TileStat *tstat;         // per tile: half-widths of the whole filter and report counts
     void *g;                 // window slots: (tile * C + ch) * slot_elems elements of the g type
     int64_t slot_elems;
     int32_t T;               // tile side
@@ -52,7 +58,6 @@ struct Job {
     int32_t fd_fp32;
     double inv_sqrt_m_d;
     double eps_full;         // floor on a^2 of the whole filter (order * eps per pass)
-    unsigned long long *counters;
     // batched launches: first global tile / FD block / scale block of this job
     int32_t tile_base, blk_base, smap_base, pad0;
 };
@@ -74,10 +79,12 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
 // batched: `jobs` is a device table of n jobs; totals are the sums of the per-job counts
 // (persistent: `grid` work-groups loop over the work list)
 hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, hipStream_t s);
-hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s);
-hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, hipStream_t s);
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, int kc, hipStream_t s);
+hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,
+                           hipStream_t s);
 
 int64_t slot_elems_for(int T, int cap);
+int chunks_for(int T, int cap);   // 256-column chunks of the widest window
 int scale_map_blocks(int64_t H, int64_t W);
 int fd_blocks_job(const Job &j);   // tile-major FD blocks, ragged edge tiles included
 

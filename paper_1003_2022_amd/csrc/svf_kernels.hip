@@ -2,8 +2,8 @@
 // filter (Chaudhury, Munoz-Barrutia, Unser, "Fast space-variant elliptical
 // filtering using box splines").
 //
-//   k_scale_map : per pixel, covariance field -> box scales (Sec. 4.2.2) and the
-//                 per-tile support half-widths that size the pre-integration windows.
+//   k_scale_map : per pixel, covariance field -> box scales (Sec. 4.2.2) and, per tile,
+//                 the support half-widths that size the pre-integration windows.
 //   k_preint    : running sums RS1..RS4 (Sec. 4.1 step (1), Algorithm 1 step 2) of one
 //                 tile's window, one work-group sweeping the rows top to bottom.
 //   k_fd        : per pixel, the 16-tap finite difference of eq. (final_eqn) (taps of
@@ -14,6 +14,8 @@
 // u4 = (-1,1)/sqrt2; the running sums step by b_k u_k = (1,0), (1,1), (0,1), (-1,1).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "svf_internal.h"
 
 namespace svf {
@@ -22,10 +24,11 @@ namespace {
 
 constexpr double kSqrt2 = 1.41421356237309504880;
 constexpr double kRsqrt2 = 0.70710678118654752440;
+constexpr int kBufWord3 = 0x00020000;   // buffer resource word 3 for gfx9-family raw loads
 
 // ---------------------------------------------------------------------------
 // LDS-only work-group barrier: orders LDS accesses without waiting for global
-// loads in flight, so the row sweep can prefetch input rows across barriers.
+// loads in flight, so the row sweep keeps its input prefetches across barriers.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void lds_barrier()
 {
@@ -47,8 +50,8 @@ __device__ __forceinline__ Window window_of(const Job &J, int tile)
     const int ti = tile / J.ntc, tj = tile - ti * J.ntc;
     const int64_t r0 = (int64_t)ti * J.T, c0 = (int64_t)tj * J.T;
     const int64_t r1 = min(r0 + (int64_t)J.T, J.H), c1 = min(c0 + (int64_t)J.T, J.W);
-    const float rx = J.tile_reach[2 * tile] * J.inv_sqrt_m;
-    const float ry = J.tile_reach[2 * tile + 1] * J.inv_sqrt_m;
+    const float rx = J.tstat[tile].rx * J.inv_sqrt_m;
+    const float ry = J.tstat[tile].ry * J.inv_sqrt_m;
     const int hx = min(J.cap, (int)ceilf(rx * 1.000001f));
     const int hy = min(J.cap, (int)ceilf(ry * 1.000001f));
     Window w;
@@ -66,6 +69,18 @@ __device__ __forceinline__ int xcd_remap(int pid, int nblocks)
 {
     const int per = nblocks >> 3;   // nblocks is a multiple of 8
     return (pid & 7) * per + (pid >> 3);
+}
+
+__device__ __forceinline__ int find_job(const Job *jobs, int n, int idx, int which)
+{
+    // largest j with base_j <= idx (bases ascending)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int b = which == 0 ? jobs[mid].tile_base : which == 1 ? jobs[mid].blk_base : jobs[mid].smap_base;
+        if (b <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -88,6 +103,7 @@ __device__ __forceinline__ void kurt_d(const double *pb, double t, double &d1, d
 // M p = c, p >= eps is p = pbar + t e, t in [lo, hi]; ||K||^2 is strictly convex in t
 // (second derivative >= 8 sum p^2 > 0), so the minimiser is an end point or the one
 // root of the derivative, found by Newton steps kept inside a shrinking bracket.
+// The scales are stored in binary32, so the root is resolved to ~1e-13 relative.
 __device__ void solve_feasible(double C11, double C12, double C22, double eps, double *a, bool &eps_act)
 {
     double pb[4];
@@ -106,16 +122,15 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
     } else if (dhi <= 0.0) {
         t = hi;
     } else {
-        const double scale = fmax(fmax(fabs(pb[0]), fabs(pb[1])), fmax(fabs(pb[2]), 1.0));
+        const double tol = 1e-13 * fmax(fmax(fabs(pb[0]), fabs(pb[1])), fmax(fabs(pb[2]), 1.0));
         t = lo + (hi - lo) * (-dlo / (dhi - dlo));
-        for (int it = 0; it < 80; ++it) {
+        for (int it = 0; it < 60; ++it) {
             double d1, d2;
             kurt_d(pb, t, d1, d2);
-            if (d1 == 0.0) break;
             if (d1 > 0.0) hi = t; else lo = t;
             double tn = t - d1 / d2;
             if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-            const bool done = fabs(tn - t) <= 4e-16 * scale || hi - lo <= 4e-16 * scale;
+            const bool done = fabs(tn - t) <= tol || hi - lo <= tol;
             t = tn;
             if (done) break;
         }
@@ -175,23 +190,29 @@ __device__ bool solve_cov(double C11, double C12, double C22, double eps, double
     return true;
 }
 
-__device__ __forceinline__ float warp_max(float v)
+__device__ __forceinline__ float wave_max(float v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return v;
 }
 
+// One block: 64 columns x (4 waves x kSmapRows) rows, inside one tile.
 __device__ void scale_map_block(const Job &J, int lb)
 {
-    const int nbx = (int)((J.W + kFdBlockX - 1) / kFdBlockX);
+    __shared__ float s_rx[4], s_ry[4];
+    __shared__ uint32_t s_cnt[4][4];
+    const int rows_per_block = 4 * kSmapRows;
+    const int nbx = (int)((J.W + kSmapCols - 1) / kSmapCols);
     const int by = lb / nbx, bx = lb - by * nbx;
-    const int64_t r = (int64_t)by * kFdBlockY + threadIdx.x / kFdBlockX;
-    const int64_t c = (int64_t)bx * kFdBlockX + threadIdx.x % kFdBlockX;
-    const bool live = r < J.H && c < J.W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)bx * kSmapCols + lane;
     float rx = 0.f, ry = 0.f;
-    bool cl = false, ea = false, bad = false;
-    if (live) {
+    uint32_t ncl = 0, nea = 0, nbad = 0, novf = 0;
+    for (int k = 0; k < kSmapRows; ++k) {
+        const int64_t r = (int64_t)by * rows_per_block + wave * kSmapRows + k;
+        if (!(r < J.H && c < J.W)) continue;
         double a[4];
+        bool cl = false, ea = false, bad = false;
         const float *fv = J.field + r * J.f_rs;
         if (J.f_kind == kScales4) {
             const float4 v = *reinterpret_cast<const float4 *>(fv + c * 4);
@@ -217,23 +238,47 @@ __device__ void scale_map_block(const Job &J, int lb)
         }
         if (!bad) {
             const double d = (a[1] + a[3]) * kRsqrt2;
-            rx = (float)(0.5 * (a[0] + d)) * 1.000001f;
-            ry = (float)(0.5 * (a[2] + d)) * 1.000001f;
+            const float px = (float)(0.5 * (a[0] + d)) * 1.000001f, py = (float)(0.5 * (a[2] + d)) * 1.000001f;
+            rx = fmaxf(rx, px);
+            ry = fmaxf(ry, py);
+            novf += fmaxf(px, py) * J.inv_sqrt_m > (float)J.cap;
         }
+        ncl += cl;
+        nea += ea;
+        nbad += bad;
     }
-    const bool ovf = live && !bad && fmaxf(rx, ry) * J.inv_sqrt_m > (float)J.cap;
-    // per-wave reduction, one atomic per wave (a block lies inside one tile)
-    const float mrx = warp_max(rx), mry = warp_max(ry);
-    const unsigned long long bcl = __ballot(cl), bea = __ballot(ea), bbad = __ballot(bad), bovf = __ballot(ovf);
-    if ((threadIdx.x & 63) == 0) {
-        const int tile = (int)((int64_t)by * kFdBlockY / J.T) * J.ntc + (int)((int64_t)bx * kFdBlockX / J.T);
-        if (mrx > 0.f) atomicMax(reinterpret_cast<unsigned int *>(J.tile_reach) + 2 * tile, __float_as_uint(mrx));
-        if (mry > 0.f) atomicMax(reinterpret_cast<unsigned int *>(J.tile_reach) + 2 * tile + 1, __float_as_uint(mry));
-        if (bcl) atomicAdd(J.counters + kClamped, (unsigned long long)__popcll(bcl));
-        if (bea) atomicAdd(J.counters + kEpsActive, (unsigned long long)__popcll(bea));
-        if (bbad) atomicAdd(J.counters + kInvalid, (unsigned long long)__popcll(bbad));
-        if (bovf) atomicAdd(J.counters + kOverflow, (unsigned long long)__popcll(bovf));
+    // block reduction, then one set of atomics per block on the tile's record
+    rx = wave_max(rx);
+    ry = wave_max(ry);
+    for (int o = 32; o > 0; o >>= 1) {
+        ncl += __shfl_xor(ncl, o);
+        nea += __shfl_xor(nea, o);
+        nbad += __shfl_xor(nbad, o);
+        novf += __shfl_xor(novf, o);
     }
+    if (lane == 0) {
+        s_rx[wave] = rx; s_ry[wave] = ry;
+        s_cnt[wave][0] = ncl; s_cnt[wave][1] = nea; s_cnt[wave][2] = nbad; s_cnt[wave][3] = novf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mx = 0.f, my = 0.f;
+        uint32_t n[4] = {0, 0, 0, 0};
+        for (int w = 0; w < 4; ++w) {
+            mx = fmaxf(mx, s_rx[w]);
+            my = fmaxf(my, s_ry[w]);
+            for (int q = 0; q < 4; ++q) n[q] += s_cnt[w][q];
+        }
+        const int tile = (int)((int64_t)by * rows_per_block / J.T) * J.ntc + (int)((int64_t)bx * kSmapCols / J.T);
+        TileStat *ts = J.tstat + tile;
+        if (mx > 0.f) atomicMax(reinterpret_cast<unsigned int *>(&ts->rx), __float_as_uint(mx));
+        if (my > 0.f) atomicMax(reinterpret_cast<unsigned int *>(&ts->ry), __float_as_uint(my));
+        if (n[0]) atomicAdd(&ts->clamped, n[0]);
+        if (n[1]) atomicAdd(&ts->eps_active, n[1]);
+        if (n[2]) atomicAdd(&ts->invalid, n[2]);
+        if (n[3]) atomicAdd(&ts->overflow, n[3]);
+    }
+    __syncthreads();   // the shared records are reused by the next block of a persistent loop
 }
 
 __global__ __launch_bounds__(256) void k_scale_map(Job J)
@@ -241,22 +286,10 @@ __global__ __launch_bounds__(256) void k_scale_map(Job J)
     scale_map_block(J, blockIdx.x);
 }
 
-__device__ __forceinline__ int find_job(const Job *jobs, int n, int idx, int which)
-{
-    // largest j with base_j <= idx (bases ascending)
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int b = which == 0 ? jobs[mid].tile_base : which == 1 ? jobs[mid].blk_base : jobs[mid].smap_base;
-        if (b <= idx) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(256) void k_scale_map_batch(const Job *jobs, int n, int total)
 {
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
-        const int j = find_job(jobs, n, b, 2);
+        const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
         const Job &J = jobs[j];
         scale_map_block(J, b - J.smap_base);
     }
@@ -274,14 +307,29 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
 //   ArI64  : wrapping 64-bit integers, no sqrt2 factors (the FD multiplies by 2);
 //   ArF32C : binary32 (hi, lo) pairs with error-free transformations
 //            (Knuth two-sum, Dekker fast-two-sum, FMA two-product).
+// Wave prefix sums use DPP (row shifts 1, 2, 4, 8 then the row broadcasts 15, 31).
 // ---------------------------------------------------------------------------
+template <int CTRL, int RM>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, RM, 0xf, true);
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v)
+{
+    const uint32_t lo = dpp32<CTRL, RM>((uint32_t)v), hi = dpp32<CTRL, RM>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 struct ArF64 {
     using T = double;
     __device__ static T zero() { return 0.0; }
     __device__ static T from(double v) { return v; }
     __device__ static T add(T a, T b) { return a + b; }
     __device__ static T s2add(T a, T b) { return fma(kSqrt2, a, b); }   // sqrt2 a + b
-    __device__ static T shfl_up(T v, int d) { return __shfl_up(v, d); }
+    template <int CTRL, int RM>
+    __device__ static T dpp(T v) { return __longlong_as_double((long long)dpp64<CTRL, RM>((uint64_t)__double_as_longlong(v))); }
     __device__ static void store(void *g, int64_t i, T v) { static_cast<double *>(g)[i] = v; }
 };
 
@@ -291,7 +339,8 @@ struct ArI64 {
     __device__ static T from(double v) { return (T)(long long)v; }
     __device__ static T add(T a, T b) { return a + b; }
     __device__ static T s2add(T a, T b) { return a + b; }
-    __device__ static T shfl_up(T v, int d) { return __shfl_up(v, d); }
+    template <int CTRL, int RM>
+    __device__ static T dpp(T v) { return dpp64<CTRL, RM>(v); }
     __device__ static void store(void *g, int64_t i, T v) { static_cast<unsigned long long *>(g)[i] = v; }
 };
 
@@ -339,132 +388,146 @@ struct ArF32C {
     __device__ static T from(double v) { const float h = (float)v; return {h, (float)(v - (double)h)}; }
     __device__ static T add(T a, T b) { return df_add(a, b); }
     __device__ static T s2add(T a, T b) { return df_add(df_mul_s2(a), b); }
-    __device__ static T shfl_up(T v, int d) { return {__shfl_up(v.hi, d), __shfl_up(v.lo, d)}; }
+    template <int CTRL, int RM>
+    __device__ static T dpp(T v)
+    {
+        return {__uint_as_float(dpp32<CTRL, RM>(__float_as_uint(v.hi))), __uint_as_float(dpp32<CTRL, RM>(__float_as_uint(v.lo)))};
+    }
     __device__ static void store(void *g, int64_t i, T v) { static_cast<float2 *>(g)[i] = make_float2(v.hi, v.lo); }
 };
 
+// inclusive prefix over the 64 lanes of a wave
 template <class A>
+__device__ __forceinline__ typename A::T wave_scan(typename A::T v)
+{
+    v = A::add(v, A::template dpp<0x111, 0xf>(v));   // row_shr:1
+    v = A::add(v, A::template dpp<0x112, 0xf>(v));   // row_shr:2
+    v = A::add(v, A::template dpp<0x114, 0xf>(v));   // row_shr:4
+    v = A::add(v, A::template dpp<0x118, 0xf>(v));   // row_shr:8
+    v = A::add(v, A::template dpp<0x142, 0xa>(v));   // row_bcast:15 into rows 1, 3
+    v = A::add(v, A::template dpp<0x143, 0xc>(v));   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+template <class A, int KC>
 struct ScanLds {
-    typename A::T p45[kMaxWindow + 2];   // previous row, index c + 1 (index 0 stays zero)
-    typename A::T pb[kMaxWindow + 2];    // previous row, index c     (index w.. stays zero)
-    typename A::T wsum[kScanChunks][kScanThreads / 64];
+    // double-buffered by row parity
+    typename A::T p45[2][KC * kScanThreads + 2];   // previous row g45 at index c + 1 (index 0 stays zero)
+    typename A::T pb[2][KC * kScanThreads + 2];    // previous row g_b at index c (index >= w stays zero)
+    typename A::T wsum[2][KC][kScanThreads / 64];
 };
 
-template <int IN>
-__device__ __forceinline__ double load_in(const void *in, int64_t idx)
-{
-    if (IN == kInF32) return (double)static_cast<const float *>(in)[idx];
-    return (double)static_cast<const unsigned short *>(in)[idx];
-}
+constexpr int kPrefetchRows = 8;
 
 // One window: rows [w.r0, w.r0 + w.h) x cols [w.c0, w.c0 + w.w), channel ch of the
 // job's pass input, zero outside the image; result (g_b, or G for integers) into
-// gout[row * w.w + col].  Thread t owns columns c = k * 256 + t.
-template <class A, int IN>
-__device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, ScanLds<A> &L)
+// gout[row * w.w + col].  Thread t owns columns c = k * 256 + t.  Input rows are
+// loaded kPrefetchRows ahead (unconditional loads at clamped addresses, masked
+// when consumed), and one LDS barrier per row orders the row exchange.
+template <class A, int IN, int KC>
+__device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, ScanLds<A, KC> &L)
 {
     using T = typename A::T;
+    using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int K = (w.w + kScanThreads - 1) / kScanThreads;
-    for (int i = t; i < kMaxWindow + 2; i += kScanThreads) { L.p45[i] = A::zero(); L.pb[i] = A::zero(); }
-    T p90[kScanChunks];
-    bool colin[kScanChunks];   // column inside the image
-    int64_t colidx[kScanChunks];
+    const int K = (w.w + kScanThreads - 1) / kScanThreads;   // <= KC
+    for (int i = t; i < KC * kScanThreads + 2; i += kScanThreads) {
+        L.p45[0][i] = A::zero(); L.pb[0][i] = A::zero();
+        L.p45[1][i] = A::zero(); L.pb[1][i] = A::zero();
+    }
+    T p90[KC];
+    bool colin[KC];
+    int64_t colidx[KC];
 #pragma unroll
-    for (int k = 0; k < kScanChunks; ++k) {
+    for (int k = 0; k < KC; ++k) {
         p90[k] = A::zero();
         const int c = k * kScanThreads + t;
         const int64_t C = w.c0 + c;
         colin[k] = k < K && c < w.w && C >= 0 && C < J.W;
-        colidx[k] = C * J.C + ch;
+        colidx[k] = min(max(C, (int64_t)0), J.W - 1) * J.C + ch;
     }
-    const unsigned char *inb = static_cast<const unsigned char *>(J.in);
-    const int esz = IN == kInF32 ? 4 : 2;
-    // prefetch the first row
-    double nxt[kScanChunks];
-    auto fetch = [&](int rr, double *dst) {
-        const int64_t R = w.r0 + rr;
-        const bool rin = rr < w.h && R >= 0 && R < J.H;
-        const void *rowp = inb + (size_t)(R * J.in_rs) * esz;
+    const E *in = static_cast<const E *>(J.in);
+    E ring[kPrefetchRows][KC];
+    auto issue = [&](int rr, E *dst) {
+        const int64_t R = min(max(w.r0 + rr, (int64_t)0), J.H - 1);
+        const E *rowp = in + R * J.in_rs;
 #pragma unroll
-        for (int k = 0; k < kScanChunks; ++k) dst[k] = (rin && colin[k]) ? load_in<IN>(rowp, colidx[k]) : 0.0;
+        for (int k = 0; k < KC; ++k) dst[k] = rowp[colidx[k]];
     };
-    fetch(0, nxt);
+#pragma unroll
+    for (int d = 0; d < kPrefetchRows; ++d) issue(d, ring[d]);
     lds_barrier();
-    for (int rr = 0; rr < w.h; ++rr) {
-        double cur[kScanChunks];
+    for (int rr0 = 0; rr0 < w.h; rr0 += kPrefetchRows) {
 #pragma unroll
-        for (int k = 0; k < kScanChunks; ++k) cur[k] = nxt[k];
-        fetch(rr + 1, nxt);   // in flight across the barriers below
-        // RS1: prefix along the row (chunk-wise wave scans, wave totals in LDS)
-        T v[kScanChunks];
+        for (int d = 0; d < kPrefetchRows; ++d) {
+            const int rr = rr0 + d;
+            if (rr >= w.h) break;   // uniform
+            const int64_t R = w.r0 + rr;
+            const bool rin = R >= 0 && R < J.H;
+            T v[KC];
 #pragma unroll
-        for (int k = 0; k < kScanChunks; ++k) {
-            v[k] = A::from(cur[k]);
-            if (k < K) {
+            for (int k = 0; k < KC; ++k) v[k] = A::from((rin && colin[k]) ? (double)ring[d][k] : 0.0);
+            issue(rr + kPrefetchRows, ring[d]);   // row rr + kPrefetchRows, clamped (value unused past the end)
+            const int pp = rr & 1;                // LDS buffer written by this row
+            // RS1: prefix along the row (wave scans, wave totals through LDS)
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const T o = A::shfl_up(v[k], d);
-                    if (lane >= d) v[k] = A::add(v[k], o);
+            for (int k = 0; k < KC; ++k) {
+                if (k < K) {
+                    v[k] = wave_scan<A>(v[k]);
+                    if (lane == 63) L.wsum[pp][k][wave] = v[k];
                 }
-                if (lane == 63) L.wsum[k][wave] = v[k];
             }
-        }
-        lds_barrier();
-        T carry = A::zero();
-        T g45[kScanChunks], gb[kScanChunks];
+            lds_barrier();
+            T carry = A::zero();
 #pragma unroll
-        for (int k = 0; k < kScanChunks; ++k) {
-            if (k < K) {
-                T off = carry;
+            for (int k = 0; k < KC; ++k) {
+                if (k < K) {
+                    T off = carry;
 #pragma unroll
-                for (int q = 0; q < kScanThreads / 64; ++q) {
-                    if (q < wave) off = A::add(off, L.wsum[k][q]);
-                    carry = A::add(carry, L.wsum[k][q]);
+                    for (int q = 0; q < kScanThreads / 64; ++q) {
+                        const T ws = L.wsum[pp][k][q];
+                        if (q < wave) off = A::add(off, ws);
+                        carry = A::add(carry, ws);
+                    }
+                    const int c = k * kScanThreads + t;
+                    const T g0 = A::add(v[k], off);
+                    const T g45 = A::s2add(g0, L.p45[pp ^ 1][c]);        // RS2: sqrt2 g0 + g45[r-1][c-1]
+                    p90[k] = A::add(g45, p90[k]);                        // RS3: g45 + g90[r-1][c]
+                    const T gb = A::s2add(p90[k], L.pb[pp ^ 1][c + 1]);  // RS4: sqrt2 g90 + gb[r-1][c+1]
+                    if (c < w.w) {
+                        L.p45[pp][c + 1] = g45;
+                        L.pb[pp][c] = gb;
+                        A::store(gout, (int64_t)rr * w.w + c, gb);
+                    }
                 }
-                const int c = k * kScanThreads + t;
-                const T g0 = A::add(v[k], off);
-                g45[k] = A::s2add(g0, L.p45[c]);          // RS2: sqrt2 g0 + g45[r-1][c-1]
-                p90[k] = A::add(g45[k], p90[k]);          // RS3: g45 + g90[r-1][c]
-                gb[k] = A::s2add(p90[k], L.pb[c + 1]);    // RS4: sqrt2 g90 + gb[r-1][c+1]
-            }
-        }
-        lds_barrier();
-#pragma unroll
-        for (int k = 0; k < kScanChunks; ++k) {
-            const int c = k * kScanThreads + t;
-            if (k < K && c < w.w) {
-                L.p45[c + 1] = g45[k];
-                L.pb[c] = gb[k];
-                A::store(gout, (int64_t)rr * w.w + c, gb[k]);
             }
         }
     }
 }
 
-template <class A, int IN>
+template <class A, int IN, int KC>
 __global__ __launch_bounds__(kScanThreads) void k_preint(Job J)
 {
-    __shared__ ScanLds<A> L;
+    __shared__ ScanLds<A, KC> L;
     const int tile = blockIdx.x / J.C, ch = blockIdx.x - tile * J.C;
     const Window w = window_of(J, tile);
     void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
-    sweep_window<A, IN>(J, ch, w, gout, L);
+    sweep_window<A, IN, KC>(J, ch, w, gout, L);
 }
 
-template <class A>
+template <class A, int KC>
 __global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, int n, int total)
 {
-    __shared__ ScanLds<A> L;
+    __shared__ ScanLds<A, KC> L;
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
-        const int j = find_job(jobs, n, b, 0);
+        const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 0));
         const Job &J = jobs[j];
         const int lt = b - J.tile_base;
         const int tile = lt / J.C, ch = lt - tile * J.C;
         const Window w = window_of(J, tile);
         void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
-        if (J.in_type == kInU16) sweep_window<A, kInU16>(J, ch, w, gout, L);
-        else sweep_window<A, kInF32>(J, ch, w, gout, L);
+        if (J.in_type == kInU16) sweep_window<A, kInU16, KC>(J, ch, w, gout, L);
+        else sweep_window<A, kInF32, KC>(J, ch, w, gout, L);
         lds_barrier();
     }
 }
@@ -472,8 +535,8 @@ __global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, 
 template <class A, int IN>
 __global__ __launch_bounds__(kScanThreads) void k_preint_window(Job J, int ch, Window w, void *g)
 {
-    __shared__ ScanLds<A> L;
-    sweep_window<A, IN>(J, ch, w, g, L);
+    __shared__ ScanLds<A, kScanChunks> L;
+    sweep_window<A, IN, kScanChunks>(J, ch, w, g, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,131 +545,296 @@ __global__ __launch_bounds__(kScanThreads) void k_preint_window(Job J, int ch, W
 // F(y) = sum_m g[m] ZP(y - m).  With m0 = round(y) and d = y - m0 in [-1/2, 1/2]^2,
 // ZP(d - k) is non-zero for 7 offsets k, and on each of the 4 triangles of the
 // cell cut by its diagonals it is one quadratic in d.  ZP is symmetric under the
-// 8 symmetries of the square, so one canonical triangle {s >= |t|} serves all:
-// d = s sa + t sb with (sa, sb) a signed pair of lattice axes, k = k1 sa + k2 sb,
-// and with the ZP element written as the density of T1(1,0)+T2(1,1)+T3(0,1)+T4(-1,1)
-// (T_k uniform on [-1/2, 1/2]) the weights on the canonical triangle are
-//   k = (0,0): (1 - s^2 - t^2)/2        k = (1,0): 1/8 + s/2 - t^2/2
-//   k = (-1,0): (1 - 2s)^2 / 8           k = (0,+-1): 1/8 +- t/2 - s^2/4 -+ s t/2 + t^2/4
-//   k = (1,+-1): (s +- t)^2 / 4
-// (they sum to 1).  Grouped by monomials, 8 F = C0 + s (Cs + s Css + t Cst) + t (Ct + t Ctt).
+// 8 symmetries of the square, so one canonical triangle {s >= t >= 0} serves all:
+// d = s sa + t sb with s = max(|d1|,|d2|), t = min(|d1|,|d2|), (sa, sb) the two
+// signed lattice axes (sa along the larger component) and k = k1 sa + k2 sb.
+// With ZP written as the density of T1(1,0)+T2(1,1)+T3(0,1)+T4(-1,1) (T_k uniform
+// on [-1/2, 1/2]), 8 x the weights on the canonical triangle are
+//   k = (0,0): 4 (1 - s^2 - t^2)        k = (1,0): 1 + 4s - 4t^2
+//   k = (-1,0): (1 - 2s)^2               k = (0,+-1): 1 - 2s^2 + 2t^2 +- 4t(1 - s)
+//   k = (1,+-1): 2 (s^2 + t^2) +- 4st
+// (they sum to 8).
+//
+// Data movement.  A work-group takes a 16 x 16 block of output pixels.  The 16
+// taps of all its pixels fall, for each tap, close to that tap of the block's
+// centre pixel shifted by the pixel's offset in the block; so for each tap the
+// group copies one 27 x 27 region of the window (the block, a margin of 4 for
+// the variation of the scales across the block, and the stencil) into LDS with
+// coalesced loads, and every lane takes its 7 samples from LDS.  A lane whose
+// stencil leaves the region (scales that change fast across the block) reads its
+// samples from the window directly instead.  Regions are double-buffered: the
+// loads for tap i+1 are in flight while tap i is computed, one barrier per tap.
+// Window samples are read with buffer loads (reads past the slot return zero).
 // ---------------------------------------------------------------------------
+constexpr int kFdSide = 16;                              // pixels per block side
+constexpr int kRegM = 4;                                 // margin for the spread of a tap over the block
+constexpr int kRegS = kFdSide + 2 * kRegM + 3;           // 27: region side
+constexpr int kRegN = kRegS * kRegS;                     // 729 samples
+constexpr int kRegLoads = (kRegN + 255) / 256;           // 3 per thread
+
 template <int PRE>
-__device__ __forceinline__ double gload(const void *g, int64_t i)
+__device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
 {
-    if (PRE == kPreF64) return static_cast<const double *>(g)[i];
-    if (PRE == kPreI64) return (double)static_cast<const long long *>(g)[i];
-    const float2 v = static_cast<const float2 *>(g)[i];
-    return (double)v.x + (double)v.y;
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+    if (PRE == kPreF64) return __builtin_bit_cast(double, v);
+    if (PRE == kPreI64) return (double)__builtin_bit_cast(long long, v);
+    const float2 f = __builtin_bit_cast(float2, v);
+    return (double)f.x + (double)f.y;
 }
 
-template <int PRE, int NCH, typename R>
-__device__ __forceinline__ void fd_pixel(const Job &J, int tile, const Window &w, int64_t r, int64_t c)
+// Tap coordinates of pixel (r, c) in window coordinates: the 8 distinct abscissae
+// (index q1 + 2 q2 + 4 q4) and ordinates (index q2 + 2 q3 + 4 q4) of n + tau - x_i
+// (Table 1: x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 4.1
+// step (2)), rounded to the nearest lattice point (IX, IY) with the remainders (DX, DY).
+template <typename R>
+__device__ __forceinline__ void tap_coords(const Job &J, const Window &w, int64_t r, int64_t c, R *DX, R *DY,
+                                           int *IX, int *IY, R &wgt)
 {
     const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
     const R m = (R)J.inv_sqrt_m_d;
     const R a1 = (R)af.x * m, a2 = (R)af.y * m, a3 = (R)af.z * m, a4 = (R)af.w * m;
     const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
-    // y_i = n + tau - x_i, in window coordinates (tau: Sec. 4.1 step (2))
     const R cx = (R)(c - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
     const R cy = (R)(r - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
-    const R wgt = (PRE == kPreI64 ? (R)2 : (R)1) / ((R)8 * a1 * a2 * a3 * a4);
-    const unsigned char *gbase = static_cast<const unsigned char *>(J.g);
-    const int64_t esz = 8;   // double, int64 and (hi, lo) float pairs are all 8 bytes
-    const void *gch[NCH];
+    wgt = (R)1 / ((R)8 * a1 * a2 * a3 * a4);
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) gch[ch] = gbase + ((int64_t)tile * J.C + ch) * J.slot_elems * esz;
-    R acc[NCH];
+    for (int i = 0; i < 8; ++i) {
+        const int b0 = i & 1, b1 = (i >> 1) & 1, b2 = (i >> 2) & 1;
+        R x = cx, y = cy;
+        if (b0) x -= a1;     // q1
+        if (b1) x -= ap2;    // q2
+        if (b2) x += ap4;    // q4
+        if (b0) y -= ap2;    // q2
+        if (b1) y -= a3;     // q3
+        if (b2) y -= ap4;    // q4
+        const R rx = rint(x), ry = rint(y);
+        DX[i] = x - rx;
+        DY[i] = y - ry;
+        IX[i] = min(max((int)rx, 1), w.w - 2);
+        IY[i] = min(max((int)ry, 1), w.h - 2);
+    }
+}
+
+// 8 x the seven ZP weights on the canonical triangle (see above) and the two
+// signed axis steps (oa along the larger remainder component, ob along the other).
+template <typename R>
+struct ZpTap {
+    R w00, w10, wm0, w01, w0m, w11, w1m;
+    int sx, sy;
+    bool hz;
+    __device__ __forceinline__ ZpTap(R dx, R dy)
+    {
+        const R adx = fabs(dx), ady = fabs(dy);
+        hz = adx >= ady;
+        const R s = fmax(adx, ady), t = fmin(adx, ady);
+        const R s2 = s * s, t2 = t * t, st = s * t, q = s2 + t2;
+        w00 = fma((R)-4, q, (R)4);
+        w10 = fma((R)4, s, (R)1) - (R)4 * t2;
+        const R u = fma((R)-2, s, (R)1);
+        wm0 = u * u;
+        const R A = fma((R)2, t2 - s2, (R)1);
+        const R B = (R)4 * (t - st);
+        w01 = A + B;
+        w0m = A - B;
+        w11 = fma((R)4, st, (R)2 * q);
+        w1m = fma((R)-4, st, (R)2 * q);
+        sx = dx >= (R)0 ? 1 : -1;
+        sy = dy >= (R)0 ? 1 : -1;
+    }
+    template <class G>
+    __device__ __forceinline__ R apply(const G &g, int base, int row) const
+    {
+        const int oa = hz ? sx : sy * row, ob = hz ? sy * row : sx;
+        R F8 = w00 * (R)g(base);
+        F8 = fma(w10, (R)g(base + oa), F8);
+        F8 = fma(wm0, (R)g(base - oa), F8);
+        F8 = fma(w01, (R)g(base + ob), F8);
+        F8 = fma(w0m, (R)g(base - ob), F8);
+        F8 = fma(w11, (R)g(base + oa + ob), F8);
+        F8 = fma(w1m, (R)g(base + oa - ob), F8);
+        return F8;
+    }
+};
+
+// Direct path for one pixel: every sample read from the window (for lanes whose
+// stencil left the staged region).  The tap coordinates are recomputed from the
+// scales one tap at a time (rolled loop), so that this path adds no registers to
+// the staged path above it.
+template <int PRE, int NCH, typename R>
+__device__ __forceinline__ void fd_direct(const Job &J, const Window &w, int64_t r, int64_t c,
+                                          const __amdgpu_buffer_rsrc_t (&rs)[NCH], R (&acc)[NCH])
+{
+    const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
+    const R m = (R)J.inv_sqrt_m_d;
+    const R a1 = (R)af.x * m, a2 = (R)af.y * m, a3 = (R)af.z * m, a4 = (R)af.w * m;
+    const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
+    const R cx = (R)(c - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
+    const R cy = (R)(r - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[ch] = (R)0;
-    const int ww = w.w;
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < 16; ++i) {
         const int q1 = i & 1, q2 = (i >> 1) & 1, q3 = (i >> 2) & 1, q4 = (i >> 3) & 1;
-        // Table 1: x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4), w_i = (-1)^(q1+q2+q3+q4) w
         R x = cx, y = cy;
         if (q1) x -= a1;
         if (q2) { x -= ap2; y -= ap2; }
         if (q3) y -= a3;
         if (q4) { x += ap4; y -= ap4; }
-        const R mx = rint(x), my = rint(y);
-        const R dx = x - mx, dy = y - my;
-        int ix = (int)mx, iy = (int)my;
-        ix = min(max(ix, 1), ww - 2);
-        iy = min(max(iy, 1), w.h - 2);
-        const int base = iy * ww + ix;
-        const R adx = fabs(dx), ady = fabs(dy);
-        const bool hz = adx >= ady;
-        const R s = hz ? adx : ady;
-        const R tt = hz ? dy : dx;
-        const int oa = hz ? (dx >= (R)0 ? 1 : -1) : (dy >= (R)0 ? ww : -ww);
-        const int ob = hz ? ww : 1;
-        const bool neg = (q1 + q2 + q3 + q4) & 1;
+        const R rx = rint(x), ry = rint(y);
+        const ZpTap<R> z(x - rx, y - ry);
+        const int base = min(max((int)ry, 1), w.h - 2) * w.w + min(max((int)rx, 1), w.w - 2);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const R g00 = (R)gload<PRE>(gch[ch], base);
-            const R g10 = (R)gload<PRE>(gch[ch], base + oa);
-            const R gm0 = (R)gload<PRE>(gch[ch], base - oa);
-            const R g01 = (R)gload<PRE>(gch[ch], base + ob);
-            const R g0m = (R)gload<PRE>(gch[ch], base - ob);
-            const R g11 = (R)gload<PRE>(gch[ch], base + oa + ob);
-            const R g1m = (R)gload<PRE>(gch[ch], base + oa - ob);
-            const R sv = g01 + g0m, sd = g11 + g1m;
-            const R C0 = (R)4 * g00 + g10 + gm0 + sv;
-            const R Cs = (R)4 * (g10 - gm0);
-            const R Ct = (R)4 * (g01 - g0m);
-            const R Css = (R)4 * (gm0 - g00) + (R)2 * (sd - sv);
-            const R Cst = (R)4 * ((g0m - g01) + (g11 - g1m));
-            const R Ctt = (R)-4 * (g00 + g10) + (R)2 * (sv + sd);
-            const R F8 = C0 + s * (Cs + s * Css + tt * Cst) + tt * (Ct + tt * Ctt);
-            acc[ch] = neg ? acc[ch] - F8 : acc[ch] + F8;
+            const __amdgpu_buffer_rsrc_t rr = rs[ch];
+            const R F8 = z.apply([&](int e) { return gload<PRE>(rr, (uint32_t)e * 8u); }, base, w.w);
+            acc[ch] = ((q1 + q2 + q3 + q4) & 1) ? acc[ch] - F8 : acc[ch] + F8;
         }
     }
-    float *o = J.out + r * J.out_rs + c * J.C;
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) o[ch] = (float)(acc[ch] * wgt);
 }
 
 template <int PRE, int NCH, typename R>
-__device__ __forceinline__ void fd_block(const Job &J, int lb)
+__device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH][kRegN])
 {
     // tile-major block order: all blocks of tile 0, then tile 1, ...
-    const int bpt_x = J.T / kFdBlockX, bpt_y = J.T / kFdBlockY, bpt = bpt_x * bpt_y;
+    const int bpt_x = J.T / kFdSide, bpt = bpt_x * bpt_x;
     const int tile = lb / bpt, rem = lb - tile * bpt;
+    if (tile >= J.ntr * J.ntc) return;   // uniform
     const int by = rem / bpt_x, bx = rem - by * bpt_x;
     const int ti = tile / J.ntc, tj = tile - ti * J.ntc;
-    const int64_t r = (int64_t)ti * J.T + by * kFdBlockY + threadIdx.x / kFdBlockX;
-    const int64_t c = (int64_t)tj * J.T + bx * kFdBlockX + threadIdx.x % kFdBlockX;
-    if (tile >= J.ntr * J.ntc || r >= J.H || c >= J.W) return;
+    const int64_t br0 = (int64_t)ti * J.T + by * kFdSide, bc0 = (int64_t)tj * J.T + bx * kFdSide;
+    if (br0 >= J.H || bc0 >= J.W) return;   // uniform: block entirely outside a ragged tile
+    const int t = threadIdx.x;
+    const int64_t r = br0 + t / kFdSide, c = bc0 + t % kFdSide;
+    const bool live = r < J.H && c < J.W;
     const Window w = window_of(J, tile);
-    fd_pixel<PRE, NCH, R>(J, tile, w, r, c);
+    const int ww = w.w;
+    // anchor: the block's centre pixel (inside the image); region origin per distinct coordinate
+    int AX[8], AY[8];
+    {
+        R dxa[8], dya[8], wa;
+        const int64_t ra = min(br0 + kFdSide / 2, J.H - 1), ca = min(bc0 + kFdSide / 2, J.W - 1);
+        tap_coords<R>(J, w, ra, ca, dxa, dya, AX, AY, wa);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            AX[i] = __builtin_amdgcn_readfirstlane(AX[i]) - (int)(ca - bc0) - 1 - kRegM;
+            AY[i] = __builtin_amdgcn_readfirstlane(AY[i]) - (int)(ra - br0) - 1 - kRegM;
+        }
+    }
+    R DX[8], DY[8], wgt;
+    int IX[8], IY[8];
+    tap_coords<R>(J, w, live ? r : br0, live ? c : bc0, DX, DY, IX, IY, wgt);
+    if (PRE == kPreI64) wgt *= (R)2;
+    const unsigned char *gbase = static_cast<const unsigned char *>(J.g);
+    const int slot_bytes = (int)(J.slot_elems * 8);
+    __amdgpu_buffer_rsrc_t rs[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+        rs[ch] = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char *>(gbase + ((int64_t)tile * J.C + ch) * J.slot_elems * 8), 0, slot_bytes,
+            kBufWord3);
+    double pre[NCH][kRegLoads];
+    auto fetch = [&](int i) {
+        const int xi = (i & 1) + 2 * ((i >> 1) & 1) + 4 * ((i >> 3) & 1);
+        const int yi = ((i >> 1) & 1) + 2 * ((i >> 2) & 1) + 4 * ((i >> 3) & 1);
+#pragma unroll
+        for (int k = 0; k < kRegLoads; ++k) {
+            const int e = t + 256 * k;
+            const int er = e / kRegS, ec = e - er * kRegS;
+            const uint32_t off = (uint32_t)((AY[yi] + er) * ww + AX[xi] + ec) * 8u;   // negative wraps: OOB -> 0
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) pre[ch][k] = gload<PRE>(rs[ch], off);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < kRegLoads; ++k) {
+            const int e = t + 256 * k;
+            if (e < kRegN) {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) lds[buf][ch][e] = pre[ch][k];
+            }
+        }
+    };
+    R acc[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] = (R)0;
+    bool outside = false;   // some stencil of this lane left its staged region
+    fetch(0);
+    stage(0);
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i + 1 < 16) fetch(i + 1);
+        const int q1 = i & 1, q2 = (i >> 1) & 1, q3 = (i >> 2) & 1, q4 = (i >> 3) & 1;
+        const int xi = q1 + 2 * q2 + 4 * q4, yi = q2 + 2 * q3 + 4 * q4;
+        const ZpTap<R> z(DX[xi], DY[yi]);
+        // sample position relative to the region (clamped; lanes outside are redone below)
+        const int lx = IX[xi] - AX[xi], ly = IY[yi] - AY[yi];
+        outside |= !(lx >= 1 && lx <= kRegS - 2 && ly >= 1 && ly <= kRegS - 2);
+        const int base = min(max(ly, 1), kRegS - 2) * kRegS + min(max(lx, 1), kRegS - 2);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const double *L = lds[i & 1][ch];
+            const R F8 = z.apply([&](int e) { return L[e]; }, base, kRegS);
+            acc[ch] = ((q1 + q2 + q3 + q4) & 1) ? acc[ch] - F8 : acc[ch] + F8;   // w_i = (-1)^(q1+..+q4) w
+            // keep this tap's arithmetic here: otherwise it is sunk into the final store
+            // block and every tap's samples stay live in registers until then
+            __asm__ volatile("" : "+v"(acc[ch]));
+        }
+        if (i + 1 < 16) {
+            stage((i + 1) & 1);
+            lds_barrier();
+        }
+    }
+    if (live && outside) fd_direct<PRE, NCH, R>(J, w, r, c, rs, acc);
+    if (live) {
+        float *o = J.out + r * J.out_rs + c * J.C;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) o[ch] = (float)(acc[ch] * wgt);
+    }
 }
 
 template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
 {
+    __shared__ double lds[2][NCH][kRegN];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    if (lb < nblocks) fd_block<PRE, NCH, R>(J, lb);
+    if (lb < nblocks) fd_block<PRE, NCH, R>(J, lb, lds);
 }
 
-template <int PRE, typename R>
+// one work-group per 16 x 16 block of any image of the table (all with NCH channels)
+template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) void k_fd_batch(const Job *jobs, int n, int total)
 {
-    for (int b = blockIdx.x; b < total; b += gridDim.x) {
-        const int j = find_job(jobs, n, b, 1);
-        const Job &J = jobs[j];
-        switch (J.C) {
-        case 1: fd_block<PRE, 1, R>(J, b - J.blk_base); break;
-        case 2: fd_block<PRE, 2, R>(J, b - J.blk_base); break;
-        case 3: fd_block<PRE, 3, R>(J, b - J.blk_base); break;
-        default: fd_block<PRE, 4, R>(J, b - J.blk_base); break;
-        }
-    }
+    __shared__ double lds[2][NCH][kRegN];
+    const int b = blockIdx.x;
+    if (b >= total) return;
+    const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 1));
+    const Job &J = jobs[j];
+    fd_block<PRE, NCH, R>(J, b - J.blk_base, lds);
 }
 
-inline int grid_for(int64_t n, int per)
+template <class A, int KC>
+hipError_t launch_preint_kc(const Job &j, int nb, hipStream_t s)
 {
-    return (int)((n + per - 1) / per);
+    if (j.in_type == kInF32)
+        hipLaunchKernelGGL((k_preint<A, kInF32, KC>), dim3(nb), dim3(kScanThreads), 0, s, j);
+    else
+        hipLaunchKernelGGL((k_preint<A, kInU16, KC>), dim3(nb), dim3(kScanThreads), 0, s, j);
+    return hipGetLastError();
+}
+
+template <class A>
+hipError_t launch_preint_t(const Job &j, hipStream_t s)
+{
+    const int nb = j.ntr * j.ntc * j.C;
+    if (nb == 0) return hipSuccess;
+    switch (chunks_for(j.T, j.cap)) {
+    case 1: return launch_preint_kc<A, 1>(j, nb, s);
+    case 2: return launch_preint_kc<A, 2>(j, nb, s);
+    case 3: return launch_preint_kc<A, 3>(j, nb, s);
+    default: return launch_preint_kc<A, 4>(j, nb, s);
+    }
 }
 
 }  // namespace
@@ -617,14 +845,19 @@ int64_t slot_elems_for(int T, int cap)
     return side * side;
 }
 
+int chunks_for(int T, int cap)
+{
+    return (T + 2 * cap + 5 + kScanThreads - 1) / kScanThreads;
+}
+
 int scale_map_blocks(int64_t H, int64_t W)
 {
-    return (int)(((W + kFdBlockX - 1) / kFdBlockX) * ((H + kFdBlockY - 1) / kFdBlockY));
+    return (int)(((W + kSmapCols - 1) / kSmapCols) * ((H + 4 * kSmapRows - 1) / (4 * kSmapRows)));
 }
 
 int fd_blocks_job(const Job &j)
 {
-    return j.ntr * j.ntc * (j.T / kFdBlockX) * (j.T / kFdBlockY);
+    return j.ntr * j.ntc * (j.T / kFdSide) * (j.T / kFdSide);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
@@ -643,18 +876,6 @@ hipError_t launch_scale_map(const Job &j, hipStream_t s)
     return hipGetLastError();
 }
 
-template <class A>
-static hipError_t launch_preint_t(const Job &j, hipStream_t s)
-{
-    const int nb = j.ntr * j.ntc * j.C;
-    if (nb == 0) return hipSuccess;
-    if (j.in_type == kInF32)
-        hipLaunchKernelGGL((k_preint<A, kInF32>), dim3(nb), dim3(kScanThreads), 0, s, j);
-    else
-        hipLaunchKernelGGL((k_preint<A, kInU16>), dim3(nb), dim3(kScanThreads), 0, s, j);
-    return hipGetLastError();
-}
-
 hipError_t launch_preint(const Job &j, hipStream_t s)
 {
     switch (j.preint) {
@@ -662,8 +883,7 @@ hipError_t launch_preint(const Job &j, hipStream_t s)
     case kPreF32C: return launch_preint_t<ArF32C>(j, s);
     case kPreI64:
         if (j.in_type != kInU16) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_preint<ArI64, kInU16>), dim3(j.ntr * j.ntc * j.C), dim3(kScanThreads), 0, s, j);
-        return hipGetLastError();
+        return launch_preint_t<ArI64>(j, s);
     }
     return hipErrorInvalidValue;
 }
@@ -692,7 +912,7 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
 }
 
 template <int PRE, typename R>
-static hipError_t launch_fd_ch(const Job &j, int nb, int grid, hipStream_t s)
+static hipError_t launch_fd_pr(const Job &j, int nb, int grid, hipStream_t s)
 {
     switch (j.C) {
     case 1: hipLaunchKernelGGL((k_fd<PRE, 1, R>), dim3(grid), dim3(256), 0, s, j, nb); break;
@@ -711,15 +931,15 @@ hipError_t launch_fd(const Job &j, hipStream_t s)
     const int grid = (nb + 7) / 8 * 8;
     if (j.fd_fp32) {
         switch (j.preint) {
-        case kPreF64: return launch_fd_ch<kPreF64, float>(j, nb, grid, s);
-        case kPreF32C: return launch_fd_ch<kPreF32C, float>(j, nb, grid, s);
-        case kPreI64: return launch_fd_ch<kPreI64, float>(j, nb, grid, s);
+        case kPreF64: return launch_fd_pr<kPreF64, float>(j, nb, grid, s);
+        case kPreF32C: return launch_fd_pr<kPreF32C, float>(j, nb, grid, s);
+        case kPreI64: return launch_fd_pr<kPreI64, float>(j, nb, grid, s);
         }
     } else {
         switch (j.preint) {
-        case kPreF64: return launch_fd_ch<kPreF64, double>(j, nb, grid, s);
-        case kPreF32C: return launch_fd_ch<kPreF32C, double>(j, nb, grid, s);
-        case kPreI64: return launch_fd_ch<kPreI64, double>(j, nb, grid, s);
+        case kPreF64: return launch_fd_pr<kPreF64, double>(j, nb, grid, s);
+        case kPreF32C: return launch_fd_pr<kPreF32C, double>(j, nb, grid, s);
+        case kPreI64: return launch_fd_pr<kPreI64, double>(j, nb, grid, s);
         }
     }
     return hipErrorInvalidValue;
@@ -733,41 +953,61 @@ hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int 
     return hipGetLastError();
 }
 
-hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s)
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, int kc, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
     grid = std::max(1, std::min(grid, total_tiles));
+#define SVF_PB(A, KC) hipLaunchKernelGGL((k_preint_batch<A, KC>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles)
+#define SVF_PB_KC(A)              \
+    switch (kc) {                 \
+    case 1: SVF_PB(A, 1); break;  \
+    case 2: SVF_PB(A, 2); break;  \
+    case 3: SVF_PB(A, 3); break;  \
+    default: SVF_PB(A, 4); break; \
+    }
     switch (preint) {
-    case kPreF64: hipLaunchKernelGGL((k_preint_batch<ArF64>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles); break;
-    case kPreF32C: hipLaunchKernelGGL((k_preint_batch<ArF32C>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles); break;
-    case kPreI64: hipLaunchKernelGGL((k_preint_batch<ArI64>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles); break;
+    case kPreF64: SVF_PB_KC(ArF64); break;
+    case kPreF32C: SVF_PB_KC(ArF32C); break;
+    case kPreI64: SVF_PB_KC(ArI64); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SVF_PB_KC
+#undef SVF_PB
+    return hipGetLastError();
+}
+
+template <int PRE, typename R>
+static hipError_t launch_fd_batch_pr(const Job *jobs, int n, int total, int nch, hipStream_t s)
+{
+    switch (nch) {
+    case 1: hipLaunchKernelGGL((k_fd_batch<PRE, 1, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
+    case 2: hipLaunchKernelGGL((k_fd_batch<PRE, 2, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
+    case 3: hipLaunchKernelGGL((k_fd_batch<PRE, 3, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
+    case 4: hipLaunchKernelGGL((k_fd_batch<PRE, 4, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, hipStream_t s)
+hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,
+                           hipStream_t s)
 {
+    (void)grid;   // one work-group per block of the work list
     if (total_blocks == 0) return hipSuccess;
-    grid = std::max(1, std::min(grid, total_blocks));
-#define SVF_FDB(P, R) hipLaunchKernelGGL((k_fd_batch<P, R>), dim3(grid), dim3(256), 0, s, jobs, n, total_blocks)
     if (fd_fp32) {
         switch (preint) {
-        case kPreF64: SVF_FDB(kPreF64, float); break;
-        case kPreF32C: SVF_FDB(kPreF32C, float); break;
-        case kPreI64: SVF_FDB(kPreI64, float); break;
-        default: return hipErrorInvalidValue;
+        case kPreF64: return launch_fd_batch_pr<kPreF64, float>(jobs, n, total_blocks, nch, s);
+        case kPreF32C: return launch_fd_batch_pr<kPreF32C, float>(jobs, n, total_blocks, nch, s);
+        case kPreI64: return launch_fd_batch_pr<kPreI64, float>(jobs, n, total_blocks, nch, s);
         }
     } else {
         switch (preint) {
-        case kPreF64: SVF_FDB(kPreF64, double); break;
-        case kPreF32C: SVF_FDB(kPreF32C, double); break;
-        case kPreI64: SVF_FDB(kPreI64, double); break;
-        default: return hipErrorInvalidValue;
+        case kPreF64: return launch_fd_batch_pr<kPreF64, double>(jobs, n, total_blocks, nch, s);
+        case kPreF32C: return launch_fd_batch_pr<kPreF32C, double>(jobs, n, total_blocks, nch, s);
+        case kPreI64: return launch_fd_batch_pr<kPreI64, double>(jobs, n, total_blocks, nch, s);
         }
     }
-#undef SVF_FDB
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace svf

@@ -64,8 +64,8 @@ int pick_tile(int64_t H, int64_t W, int requested)
 {
     if (requested == 64 || requested == 128 || requested == 256) return requested;
     auto tiles = [&](int64_t T) { return ((H + T - 1) / T) * ((W + T - 1) / T); };
-    if (tiles(256) >= 96) return 256;
-    if (tiles(128) >= 48) return 128;
+    // several windows per CU: the row sweeps of different windows hide each other's latency
+    if (tiles(128) >= 256) return 128;
     return 64;
 }
 
@@ -118,9 +118,8 @@ Plan plan_for(const svf_image *in, int order, const svf_opts *o)
     p.ntr = (int)((in->H + p.T - 1) / p.T);
     p.ntc = (int)((in->W + p.T - 1) / p.T);
     p.slot = slot_elems_for(p.T, p.cap);
-    p.off_counters = 0;
-    p.off_reach = 256;
-    p.off_scales = align_up(p.off_reach + (size_t)p.ntr * p.ntc * 2 * sizeof(float), 256);
+    p.off_tstat = 0;
+    p.off_scales = align_up((size_t)p.ntr * p.ntc * sizeof(TileStat), 256);
     p.off_g = align_up(p.off_scales + (size_t)in->H * in->W * 4 * sizeof(float), 256);
     p.bytes = p.off_g + (size_t)p.ntr * p.ntc * in->channels * p.slot * 8;
     (void)order;
@@ -150,6 +149,33 @@ svf_status ensure_workspace(svf_ctx *ctx, size_t bytes)
     return SVF_OK;
 }
 
+svf_status ensure_pinned(svf_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->pinned_bytes) return SVF_OK;
+    if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
+    ctx->host_pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    const size_t n = std::max(bytes, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(&ctx->host_pinned, n, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ctx, SVF_ENOMEM, "pinned host buffer: %s", hipGetErrorString(e));
+    ctx->pinned_bytes = n;
+    return SVF_OK;
+}
+
+void fill_report(const TileStat *ts, size_t nt, int order, svf_report *rep)
+{
+    std::memset(rep, 0, sizeof *rep);
+    float mx = 0.f;
+    for (size_t i = 0; i < nt; ++i) {
+        rep->clamped_px += ts[i].clamped;
+        rep->eps_active_px += ts[i].eps_active;
+        rep->invalid_px += ts[i].invalid;
+        rep->overflow_px += ts[i].overflow;
+        mx = std::max(mx, std::max(ts[i].rx, ts[i].ry));
+    }
+    rep->max_reach_px = mx / std::sqrt((double)order);
+}
+
 // Fill the parts of a job common to every pass.
 Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
              unsigned char *ws)
@@ -172,7 +198,7 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
         j.scales = reinterpret_cast<const float *>(ws + p.off_scales);
         j.sc_rs = in->W * 4;
     }
-    j.tile_reach = reinterpret_cast<float *>(ws + p.off_reach);
+    j.tstat = reinterpret_cast<TileStat *>(ws + p.off_tstat);
     j.g = ws + p.off_g;
     j.slot_elems = p.slot;
     j.T = p.T;
@@ -183,7 +209,6 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
     j.inv_sqrt_m_d = 1.0 / std::sqrt((double)order);
     j.fd_fp32 = o->fd_fp32 ? 1 : 0;
     j.eps_full = o->eps_px2 * order;
-    j.counters = reinterpret_cast<unsigned long long *>(ws + p.off_counters);
     j.preint = o->preint;
     return j;
 }
@@ -234,7 +259,7 @@ svf_status svf_create(svf_ctx **out, int device, size_t hbm_budget_bytes)
     if (!c) return SVF_ENOMEM;
     c->device = device;
     c->budget = hbm_budget_bytes;
-    if (hipHostMalloc(&c->host_pinned, 1 << 20, hipHostMallocDefault) != hipSuccess) {
+    if (ensure_pinned(c, (size_t)1 << 20) != SVF_OK) {
         delete c;
         return SVF_ENOMEM;
     }
@@ -246,6 +271,7 @@ svf_status svf_destroy(svf_ctx *ctx)
 {
     if (!ctx) return SVF_EINVAL;
     hipSetDevice(ctx->device);
+    if (ctx->server) svf_server_stop(ctx);
     hipDeviceSynchronize();
     svf_batch_release(ctx);
     for (auto &p : ctx->pending) {
@@ -394,25 +420,13 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
         if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
     }
     if (rep) {
-        const size_t nreach = (size_t)p.ntr * p.ntc * 2;
-        if (32 + nreach * 4 <= (1u << 20)) {
-            e = hipMemcpyAsync(ctx->host_pinned, ws, 32, hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(static_cast<char *>(ctx->host_pinned) + 32, ws + p.off_reach, nreach * 4,
-                                   hipMemcpyDeviceToHost, stream);
-        }
+        const size_t nt = (size_t)p.ntr * p.ntc;
+        svf_status rs = ensure_pinned(ctx, nt * sizeof(TileStat));
+        if (rs) return rs;
+        e = hipMemcpyAsync(ctx->host_pinned, ws + p.off_tstat, nt * sizeof(TileStat), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "report");
-        const unsigned long long *cn = static_cast<const unsigned long long *>(ctx->host_pinned);
-        rep->clamped_px = (int64_t)cn[kClamped];
-        rep->eps_active_px = (int64_t)cn[kEpsActive];
-        rep->invalid_px = (int64_t)cn[kInvalid];
-        rep->overflow_px = (int64_t)cn[kOverflow];
-        const float *rr = reinterpret_cast<const float *>(static_cast<const char *>(ctx->host_pinned) + 32);
-        float mx = 0.f;
-        if (32 + nreach * 4 <= (1u << 20))
-            for (size_t i = 0; i < nreach; ++i) mx = std::max(mx, rr[i]);
-        rep->max_reach_px = mx / std::sqrt((double)order);
+        fill_report(static_cast<const TileStat *>(ctx->host_pinned), nt, order, rep);
         if (rep->invalid_px > 0) return fail(ctx, SVF_EINVAL, "%lld pixels with an invalid field entry", (long long)rep->invalid_px);
         if (rep->overflow_px > 0)
             return fail(ctx, SVF_ERANGE, "%lld pixels exceed max_reach_px = %d", (long long)rep->overflow_px, o.max_reach_px);

@@ -19,7 +19,8 @@ struct svf_ctx {
     void *ws = nullptr;                // device workspace (grown on demand)
     size_t ws_bytes = 0;
     uint64_t ws_generation = 0;        // bumped when the workspace moves (invalidates graphs)
-    void *host_pinned = nullptr;       // 1 MiB of pinned host memory for reports / descriptors
+    void *host_pinned = nullptr;       // pinned host memory for reports (grown on demand)
+    size_t pinned_bytes = 0;
     std::string err;
     bool timing = false;
     struct Rec {
@@ -31,6 +32,7 @@ struct svf_ctx {
     double tot_ms[kNumKernelClasses] = {};
     int64_t count[kNumKernelClasses] = {};
     void *batch = nullptr;             // svf::BatchState
+    void *server = nullptr;            // serving loop (svf_server.cpp)
     hipEvent_t take_event();
 };
 
@@ -39,7 +41,7 @@ namespace svf {
 struct Plan {
     int T = 0, cap = 0, ntr = 0, ntc = 0;
     int64_t slot = 0;
-    size_t off_counters = 0, off_reach = 0, off_scales = 0, off_g = 0, bytes = 0;
+    size_t off_tstat = 0, off_scales = 0, off_g = 0, bytes = 0;
 };
 
 svf_status fail(svf_ctx *ctx, svf_status st, const char *fmt, ...);
@@ -51,6 +53,8 @@ svf_status check_image(svf_ctx *ctx, const svf_image *im, const char *what, bool
 svf_status check_field(svf_ctx *ctx, const svf_field *f, int64_t H, int64_t W);
 Plan plan_for(const svf_image *in, int order, const svf_opts *o);
 svf_status ensure_workspace(svf_ctx *ctx, size_t bytes);
+svf_status ensure_pinned(svf_ctx *ctx, size_t bytes);
+void fill_report(const TileStat *ts, size_t nt, int order, svf_report *rep);
 Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
              unsigned char *ws);
 

@@ -1,1 +1,434 @@
-// svf_server.cpp -- placeholder
+// svf_server.cpp -- serving loop with continuous batching (svf_server_*).
+//
+// A scheduler thread owns a device arena and its own HIP stream.  Submitted
+// requests wait in a FIFO queue; the head is admitted when a slot is free and
+// its footprint (per-tile records, scales, one window slot per tile and
+// channel) fits in the arena.  Each step enqueues
+//   fill(tile records of the newly admitted) -> scale map(newly admitted)
+//   -> pre-integration(one pass of every request in flight)
+//   -> finite difference(the same pass)
+// through the persistent batched kernels, with the descriptor tables staged in
+// pinned memory and uploaded on the server stream (two table sets, alternating).
+// A request at pass p in step k is at pass p+1 in step k+1; a request whose last
+// pass ran in step k is completed, and its arena range freed, once the host has
+// seen step k's event.  Steps are pipelined one deep: step k+1 is enqueued before
+// the host waits for step k.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "svf_runtime_internal.h"
+
+using namespace svf;
+
+namespace {
+
+constexpr int kTables = 1 + kMaxChannels;   // scale map + one table per channel count
+constexpr int kPersistentScale = 4096;
+constexpr int kPersistentPreint = 2048;
+constexpr int kPersistentFd = 16384;
+
+double now_us()
+{
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// First-fit allocator over [0, size) with coalescing.
+struct Arena {
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t size = 0;
+    void reset(size_t n)
+    {
+        free_.clear();
+        size = n;
+        if (n) free_[0] = n;
+    }
+    bool alloc(size_t n, size_t &off)
+    {
+        n = align_up(n, 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = align_up(n, 256);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Req {
+    svf_request r;
+    Plan plan;
+    size_t bytes = 0, off = 0;
+    int pass = -1;                 // next pass to run; -1: not admitted
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int status = SVF_EBUSY;
+    bool done = false;
+};
+
+struct StepBuf {
+    Job *d = nullptr, *h = nullptr;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    std::vector<uint64_t> finishing;   // requests whose last pass runs in this step
+    std::vector<uint64_t> running;
+};
+
+struct Server {
+    svf_ctx *ctx = nullptr;
+    svf_server_cfg cfg{};
+    hipStream_t stream = nullptr;
+    unsigned char *arena_base = nullptr;
+    Arena arena;
+    int cap = 0;                       // jobs per table
+    StepBuf buf[2];
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::vector<uint64_t> inflight;
+    std::unordered_map<uint64_t, Req> reqs;
+    uint64_t next_id = 1;
+    bool stopping = false;
+    std::thread th;
+    svf_server_stats_t stats{};
+    double busy_since = -1;
+    std::string err;
+};
+
+Server *srv(svf_ctx *ctx) { return static_cast<Server *>(ctx->server); }
+
+// Launch one step from the tables in `b`; returns false on a HIP error.
+bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *counts, const int *tot_tiles,
+                 const int *tot_blk, int kc)
+{
+    hipError_t e = hipMemcpyAsync(b.d, b.h, sizeof(Job) * kTables * S->cap, hipMemcpyHostToDevice, S->stream);
+    if (e != hipSuccess) return false;
+    // zero the tile records of the newly admitted requests
+    for (int i = 0; i < nsmap && e == hipSuccess; ++i) {
+        const Job &j = b.h[i];
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(j.tstat), 0u,
+                            (int64_t)j.ntr * j.ntc * (int64_t)(sizeof(TileStat) / 4), S->stream);
+    }
+    if (e == hipSuccess && nsmap) e = launch_scale_map_batch(b.d, nsmap, tot_smap, kPersistentScale, S->stream);
+    for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
+        if (counts[ch]) e = launch_preint_batch(b.d + ch * S->cap, counts[ch], tot_tiles[ch], kPersistentPreint,
+                                                S->cfg.opts.preint, kc, S->stream);
+    for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
+        if (counts[ch]) e = launch_fd_batch(b.d + ch * S->cap, counts[ch], tot_blk[ch], kPersistentFd,
+                                            S->cfg.opts.preint, S->cfg.opts.fd_fp32, ch, S->stream);
+    if (e == hipSuccess) e = hipEventRecord(b.ev, S->stream);
+    return e == hipSuccess;
+}
+
+// Host side of a finished step: complete its finishing requests.
+void retire(Server *S, StepBuf &b)
+{
+    if (!b.pending) return;
+    hipError_t e = hipEventSynchronize(b.ev);
+    const double t = now_us();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (uint64_t id : b.finishing) {
+        Req &q = S->reqs[id];
+        q.done = true;
+        q.status = e == hipSuccess ? SVF_OK : SVF_EHIP;
+        q.t_done = t;
+        S->arena.release(q.off, q.bytes);
+        S->stats.completed++;
+        S->stats.pixels += q.r.out.H * q.r.out.W * q.r.out.channels;
+        S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), id));
+    }
+    b.finishing.clear();
+    b.running.clear();
+    b.pending = false;
+    if (S->inflight.empty() && S->busy_since >= 0) {
+        S->stats.busy_us += t - S->busy_since;
+        S->busy_since = -1;
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+}
+
+void loop(Server *S)
+{
+    hipSetDevice(S->ctx->device);
+    int k = 0;
+    for (;;) {
+        StepBuf &b = S->buf[k & 1];
+        retire(S, b);   // this buffer's previous step (two steps ago) must be done before reuse
+        std::vector<std::pair<uint64_t, Req *>> running;   // element pointers stay valid across rehash
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            // admission: FIFO, slot limit, arena fit
+            while (!S->queue.empty() && (int)S->inflight.size() < S->cfg.max_inflight) {
+                Req &q = S->reqs[S->queue.front()];
+                size_t off;
+                if (!S->arena.alloc(q.bytes, off)) break;
+                q.off = off;
+                q.pass = 0;
+                q.t_admit = now_us();
+                S->inflight.push_back(S->queue.front());
+                S->queue.pop_front();
+            }
+            // requests in flight with a pass still to run
+            for (uint64_t id : S->inflight) {
+                Req &q = S->reqs[id];
+                if (q.pass < q.r.order) running.emplace_back(id, &q);
+            }
+            if (running.empty()) {
+                StepBuf &o = S->buf[(k + 1) & 1];
+                if (o.pending) {
+                    lk.unlock();
+                    retire(S, o);
+                    continue;
+                }
+                if (S->stopping && S->queue.empty() && S->inflight.empty()) break;
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+            if (S->busy_since < 0) S->busy_since = now_us();
+        }
+        // ---- build the tables (only this thread writes q.pass / q.off) ----
+        int counts[kTables] = {}, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
+        int tot_smap = 0, kc = 1;
+        int nsmap = 0;
+        for (auto &pr : running) {
+            const uint64_t id = pr.first;
+            Req &q = *pr.second;
+            const Plan &p = q.plan;
+            Plan pp = p;
+            pp.off_tstat = q.off + p.off_tstat;
+            pp.off_scales = q.off + p.off_scales;
+            pp.off_g = q.off + p.off_g;
+            kc = std::max(kc, chunks_for(p.T, p.cap));
+            Job base = base_job(&q.r.in, &q.r.field, q.r.order, &S->cfg.opts, pp, S->arena_base);
+            base.out = static_cast<float *>(q.r.out.data);
+            base.out_rs = q.r.out.row_stride;
+            if (q.pass == 0) {
+                Job js = base;
+                js.smap_base = tot_smap;
+                tot_smap += scale_map_blocks(q.r.in.H, q.r.in.W);
+                b.h[nsmap++] = js;
+            }
+            Job jp = base;
+            if (q.pass > 0) {
+                jp.in = q.r.out.data;
+                jp.in_rs = q.r.out.row_stride;
+                jp.in_type = kInF32;
+            }
+            const int ch = q.r.in.channels;
+            jp.tile_base = tot_tiles[ch];
+            jp.blk_base = tot_blk[ch];
+            tot_tiles[ch] += p.ntr * p.ntc * ch;
+            tot_blk[ch] += fd_blocks_job(jp);
+            b.h[ch * S->cap + counts[ch]++] = jp;
+            q.pass++;
+            if (q.pass == q.r.order) b.finishing.push_back(id);
+            b.running.push_back(id);
+        }
+        if (!launch_step(S, b, nsmap, tot_smap, counts, tot_tiles, tot_blk, kc)) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->err = "step launch failed";
+        }
+        b.pending = true;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats.steps++;
+        }
+        ++k;
+    }
+    retire(S, S->buf[0]);
+    retire(S, S->buf[1]);
+}
+
+}  // namespace
+
+extern "C" {
+
+svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
+{
+    if (!ctx || !cfg) return SVF_EINVAL;
+    ctx->err.clear();
+    if (ctx->server) return fail(ctx, SVF_EINVAL, "server already running");
+    svf_server_cfg c = *cfg;
+    if (c.max_inflight <= 0) c.max_inflight = 16;
+    if (c.queue_capacity <= 0) c.queue_capacity = 1024;
+    if (c.opts.tile == 0) c.opts.tile = 256;
+    if (c.opts.preint != SVF_PRE_F64 && c.opts.preint != SVF_PRE_F32C)
+        return fail(ctx, SVF_EUNSUPPORTED, "the server offers SVF_PRE_F64 and SVF_PRE_F32C");
+    svf_status st = check_opts(ctx, &c.opts, c.opts.tile);
+    if (st) return st;
+    if (c.hbm_budget_bytes == 0) return fail(ctx, SVF_EINVAL, "hbm_budget_bytes must be > 0");
+    hipSetDevice(ctx->device);
+    Server *S = new Server();
+    S->ctx = ctx;
+    S->cfg = c;
+    S->cap = c.max_inflight;
+    hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&S->arena_base, c.hbm_budget_bytes);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipMalloc(&S->buf[i].d, sizeof(Job) * kTables * S->cap);
+        if (e == hipSuccess) e = hipHostMalloc(&S->buf[i].h, sizeof(Job) * kTables * S->cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&S->buf[i].ev, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        for (auto &b : S->buf) {
+            if (b.d) hipFree(b.d);
+            if (b.h) hipHostFree(b.h);
+            if (b.ev) hipEventDestroy(b.ev);
+        }
+        if (S->arena_base) hipFree(S->arena_base);
+        if (S->stream) hipStreamDestroy(S->stream);
+        delete S;
+        return fail(ctx, SVF_ENOMEM, "server allocation: %s", hipGetErrorString(e));
+    }
+    S->arena.reset(c.hbm_budget_bytes);
+    ctx->server = S;
+    S->th = std::thread(loop, S);
+    return SVF_OK;
+}
+
+svf_status svf_server_submit(svf_ctx *ctx, const svf_request *req, uint64_t *id)
+{
+    if (!ctx || !req || !id) return SVF_EINVAL;
+    Server *S = srv(ctx);
+    if (!S) return fail(ctx, SVF_EINVAL, "server not running");
+    // argument checks (same rules as svf_filter)
+    svf_status st = check_image(ctx, &req->in, "in", false);
+    if (!st) st = check_image(ctx, &req->out, "out", true);
+    if (!st && (req->out.H != req->in.H || req->out.W != req->in.W || req->out.channels != req->in.channels))
+        st = fail(ctx, SVF_EINVAL, "out must match in");
+    if (!st) st = check_field(ctx, &req->field, req->in.H, req->in.W);
+    if (!st && (req->order < 1 || req->order > 3)) st = fail(ctx, SVF_EINVAL, "order must be 1..3");
+    if (!st && (req->in.H == 0 || req->in.W == 0)) st = fail(ctx, SVF_EINVAL, "empty image");
+    if (st) return st;
+    Req q;
+    q.r = *req;
+    q.plan = plan_for(&req->in, req->order, &S->cfg.opts);
+    q.bytes = q.plan.bytes;
+    q.t_submit = now_us();
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.submitted++;
+    if (S->stopping) return fail(ctx, SVF_ECANCELLED, "server stopping");
+    if (q.bytes > S->arena.size) {
+        S->stats.rejected++;
+        return fail(ctx, SVF_ENOMEM, "request needs %zu bytes, budget is %zu", q.bytes, S->arena.size);
+    }
+    if ((int)S->queue.size() >= S->cfg.queue_capacity) {
+        S->stats.rejected++;
+        return fail(ctx, SVF_EBUSY, "queue full");
+    }
+    const uint64_t nid = S->next_id++;
+    S->reqs.emplace(nid, q);
+    S->queue.push_back(nid);
+    *id = nid;
+    S->cv_work.notify_all();
+    return SVF_OK;
+}
+
+static void fill_result(const Req &q, svf_result *res)
+{
+    res->status = q.status;
+    res->done = q.done ? 1 : 0;
+    res->t_submit_us = q.t_submit;
+    res->t_admit_us = q.t_admit;
+    res->t_done_us = q.t_done;
+}
+
+svf_status svf_server_poll(svf_ctx *ctx, uint64_t id, svf_result *res)
+{
+    if (!ctx || !res) return SVF_EINVAL;
+    Server *S = srv(ctx);
+    if (!S) return fail(ctx, SVF_EINVAL, "server not running");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(ctx, SVF_EINVAL, "unknown request id");
+    fill_result(it->second, res);
+    return SVF_OK;
+}
+
+svf_status svf_server_wait(svf_ctx *ctx, uint64_t id, svf_result *res, double timeout_s)
+{
+    if (!ctx || !res) return SVF_EINVAL;
+    Server *S = srv(ctx);
+    if (!S) return fail(ctx, SVF_EINVAL, "server not running");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(ctx, SVF_EINVAL, "unknown request id");
+    auto pred = [&] { return S->reqs[id].done; };
+    if (timeout_s < 0) S->cv_done.wait(lk, pred);
+    else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) {
+        fill_result(S->reqs[id], res);
+        return SVF_EBUSY;
+    }
+    fill_result(S->reqs[id], res);
+    return SVF_OK;
+}
+
+svf_status svf_server_stats(svf_ctx *ctx, svf_server_stats_t *stats)
+{
+    if (!ctx || !stats) return SVF_EINVAL;
+    Server *S = srv(ctx);
+    if (!S) return fail(ctx, SVF_EINVAL, "server not running");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *stats = S->stats;
+    if (S->busy_since >= 0) stats->busy_us += now_us() - S->busy_since;
+    return SVF_OK;
+}
+
+svf_status svf_server_stop(svf_ctx *ctx)
+{
+    if (!ctx) return SVF_EINVAL;
+    Server *S = srv(ctx);
+    if (!S) return SVF_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stopping = true;
+        S->cv_work.notify_all();
+    }
+    S->th.join();
+    hipStreamSynchronize(S->stream);
+    for (auto &b : S->buf) {
+        hipFree(b.d);
+        hipHostFree(b.h);
+        hipEventDestroy(b.ev);
+    }
+    hipFree(S->arena_base);
+    hipStreamDestroy(S->stream);
+    delete S;
+    ctx->server = nullptr;
+    return SVF_OK;
+}
+
+}  // extern "C"
