@@ -127,12 +127,16 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
         for (int it = 0; it < 60; ++it) {
             double d1, d2;
             kurt_d(pb, t, d1, d2);
+            const double step = d1 / d2;
+            // converged: take the last (sub-tolerance) step; tested before the bracket
+            // update, since a step below one ulp of t would otherwise read as leaving
+            // the bracket and restart bisection from its far end
+            if (fabs(step) <= tol) { t = fmin(fmax(t - step, lo), hi); break; }
             if (d1 > 0.0) hi = t; else lo = t;
-            double tn = t - d1 / d2;
+            double tn = t - step;
             if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-            const bool done = fabs(tn - t) <= tol || hi - lo <= tol;
             t = tn;
-            if (done) break;
+            if (hi - lo <= tol) break;
         }
     }
     const double p[4] = {pb[0] + t, pb[1] - t, pb[2] + t, pb[3] - t};
@@ -571,6 +575,8 @@ constexpr int kRegM = 4;                                 // margin for the sprea
 constexpr int kRegS = kFdSide + 2 * kRegM + 3;           // 27: region side
 constexpr int kRegN = kRegS * kRegS;                     // 729 samples
 constexpr int kRegLoads = (kRegN + 255) / 256;           // 3 per thread
+constexpr int kRegPad = kRegLoads * 256;                 // 768: LDS stride of a region (branch-free staging)
+constexpr int kFdPrefetch = 3;                           // taps whose loads are in flight
 
 template <int PRE>
 __device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
@@ -693,7 +699,7 @@ __device__ __forceinline__ void fd_direct(const Job &J, const Window &w, int64_t
 }
 
 template <int PRE, int NCH, typename R>
-__device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH][kRegN])
+__device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH][kRegPad])
 {
     // tile-major block order: all blocks of tile 0, then tile 1, ...
     const int bpt_x = J.T / kFdSide, bpt = bpt_x * bpt_x;
@@ -732,39 +738,39 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         rs[ch] = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<unsigned char *>(gbase + ((int64_t)tile * J.C + ch) * J.slot_elems * 8), 0, slot_bytes,
             kBufWord3);
-    double pre[NCH][kRegLoads];
+    // loads of tap j go to register slot j % kFdPrefetch; tap j is fetched kFdPrefetch
+    // taps before it is staged
+    double pre[kFdPrefetch][NCH][kRegLoads];
     auto fetch = [&](int i) {
         const int xi = (i & 1) + 2 * ((i >> 1) & 1) + 4 * ((i >> 3) & 1);
         const int yi = ((i >> 1) & 1) + 2 * ((i >> 2) & 1) + 4 * ((i >> 3) & 1);
 #pragma unroll
         for (int k = 0; k < kRegLoads; ++k) {
-            const int e = t + 256 * k;
+            const int e = t + 256 * k;   // entries past kRegN are loaded and staged but never read
             const int er = e / kRegS, ec = e - er * kRegS;
             const uint32_t off = (uint32_t)((AY[yi] + er) * ww + AX[xi] + ec) * 8u;   // negative wraps: OOB -> 0
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) pre[ch][k] = gload<PRE>(rs[ch], off);
+            for (int ch = 0; ch < NCH; ++ch) pre[i % kFdPrefetch][ch][k] = gload<PRE>(rs[ch], off);
         }
     };
-    auto stage = [&](int buf) {
+    auto stage = [&](int i) {
 #pragma unroll
         for (int k = 0; k < kRegLoads; ++k) {
-            const int e = t + 256 * k;
-            if (e < kRegN) {
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) lds[buf][ch][e] = pre[ch][k];
-            }
+            for (int ch = 0; ch < NCH; ++ch) lds[i & 1][ch][t + 256 * k] = pre[i % kFdPrefetch][ch][k];
         }
     };
     R acc[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[ch] = (R)0;
     bool outside = false;   // some stencil of this lane left its staged region
-    fetch(0);
+#pragma unroll
+    for (int j = 0; j < kFdPrefetch; ++j) fetch(j);
     stage(0);
     lds_barrier();
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        if (i + 1 < 16) fetch(i + 1);
+        if (i + kFdPrefetch < 16) fetch(i + kFdPrefetch);
         const int q1 = i & 1, q2 = (i >> 1) & 1, q3 = (i >> 2) & 1, q4 = (i >> 3) & 1;
         const int xi = q1 + 2 * q2 + 4 * q4, yi = q2 + 2 * q3 + 4 * q4;
         const ZpTap<R> z(DX[xi], DY[yi]);
@@ -782,7 +788,7 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
             __asm__ volatile("" : "+v"(acc[ch]));
         }
         if (i + 1 < 16) {
-            stage((i + 1) & 1);
+            stage(i + 1);
             lds_barrier();
         }
     }
@@ -797,7 +803,7 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
 template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
 {
-    __shared__ double lds[2][NCH][kRegN];
+    __shared__ double lds[2][NCH][kRegPad];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     if (lb < nblocks) fd_block<PRE, NCH, R>(J, lb, lds);
 }
@@ -806,7 +812,7 @@ __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
 template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) void k_fd_batch(const Job *jobs, int n, int total)
 {
-    __shared__ double lds[2][NCH][kRegN];
+    __shared__ double lds[2][NCH][kRegPad];
     const int b = blockIdx.x;
     if (b >= total) return;
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 1));
