@@ -1,19 +1,37 @@
-"""Benchmark: 4096 x 4096 FP32 image, ZP (N = 4) filter of order 2, per-pixel
-covariance field sigma in [1, 32] px, elongation in [1, 6], orientation in
-[0, pi) (smooth seeded field, correlation length 256 px), FP64 pre-integration
-and FP64 finite difference, on one MI355X.
+"""Benchmark of the space-variant box-spline filter on one MI355X.
 
-Prints one JSON line (see the design doc for the fields).  A step is one whole
-svf_filter call (scale map, and per pass the pre-integration and the finite
-difference) with the input, field and output resident in HBM.
+Main line (the `value`): a 4096 x 4096 FP32 image, ZP (N = 4) filter of order 2,
+per-pixel covariance field sigma in [1, 32] px, elongation in [1, 6],
+orientation in [0, pi) (smooth seeded field, correlation length 256 px), FP64
+pre-integration and FP64 finite difference.  A step is one whole svf_filter
+call (scale map, and per pass the pre-integration and the finite difference)
+with input, field and output resident in HBM.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--calib-copy]
+Beside it, in the same JSON line:
+  roofline      the finite-difference kernel (the dominant one) against the FP64
+                vector peak, its launch time measured with HIP events on the
+                launch stream, and its HBM traffic per launch from the committed
+                rocprofv3 counter summary (null once the kernel source changed);
+  batch         64 images of sizes drawn from {256, 512, 1024, 2048}^2, order 2,
+                each with its own field: one graph-replayed batched launch
+                against 64 svf_filter calls;
+  serving       Poisson arrivals of 3-channel images 512..4096 px (aspect 1:1 to
+                1:2), orders 1-3: the continuous-batching server against a FIFO
+                of svf_filter calls (one image per launch), p50/p99 latency from
+                arrival, and the saturated throughput of both;
+  cpu_baseline  the CPU FP64 oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve]
+                    [--calib-copy] [--preint f64|f32c] [--tile T] [--qps Q] [--serve-seconds S]
 """
 from __future__ import annotations
 
 import argparse
+import collections
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 from pathlib import Path
@@ -31,13 +49,31 @@ ORDER = 2
 SEED = 3000
 # algorithmic work per output pixel and pass (derivations in the design doc)
 FD_FLOPS_PER_PX = 640          # FP64 flops (FMA = 2) of the 16-tap difference with 7-point ZP interpolation
-FD_BYTES_PER_PX = 16 + 8 + 4   # scales (float4) + one pre-integrated sample + output (float32)
-PREINT_BYTES_PER_PX = 4 + 8    # input sample + pre-integrated sample, per window sample
 ALGO_BYTES_PER_PX_PASS = 36    # f 4 + field 12 + g write 8 + g read 8 + out 4
+KERNEL_SRC = ROOT / "paper_1003_2022_amd" / "csrc" / "svf_kernels.hip"
+TRAFFIC_SUMMARY = ROOT / "profiles" / "k_fd_4096sq_order2_hbm_traffic.txt"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(KERNEL_SRC.read_bytes()).hexdigest()[:16]
+
+
+def fd_traffic_per_launch():
+    """HBM bytes per k_fd launch from the committed counter summary, if it was taken on this kernel source."""
+    if not TRAFFIC_SUMMARY.exists():
+        return None, "no counter summary"
+    txt = TRAFFIC_SUMMARY.read_text()
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"k_fd_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (h and b):
+        return None, "counter summary incomplete"
+    if h.group(1) != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return float(b.group(1)), str(TRAFFIC_SUMMARY.relative_to(ROOT))
 
 
 def cpu_baseline(img, fld, kind):
@@ -45,8 +81,8 @@ def cpu_baseline(img, fld, kind):
     import oracle
 
     oracle.build()
-    r0 = c0 = 1536
-    side = 1024
+    r0 = c0 = 512
+    side = 3072
     t = time.perf_counter()
     out = oracle.filter_region(img, fld, kind, ORDER, (r0, c0, side, side))
     dt = time.perf_counter() - t
@@ -57,10 +93,195 @@ def cpu_baseline(img, fld, kind):
         "cores": cores,
         "kind": "oracle",
         "sample": f"{side}x{side} output pixels at ({r0},{c0}) of the same 4096x4096 order-2 workload "
-                  f"(the oracle computes the pass-1 region the sample depends on), {dt:.1f} s",
+                  f"(the oracle also computes the pass-1 region the sample depends on), {dt:.1f} s",
         "checksum": float(np.mean(out)),
     }
 
+
+# ----------------------------------------------------------------------------- batched launch leg
+
+def batch_leg(P, I, ctx, img_dev, torch, reps=5):
+    """64 images, sizes from {256, 512, 1024, 2048}^2, order 2, own fields (sigma 1-16, rho 1-4)."""
+    dev = img_dev.device
+    rng = np.random.default_rng(SEED + 4)
+    sides = rng.choice([256, 512, 1024, 2048], size=64)
+    t0 = time.perf_counter()
+    pool = torch.from_numpy(I.srt_field(2048, 2048, SEED + 4, (1.0, 16.0), (1.0, 4.0), corr_len=64.0)).to(dev)
+    log(f"batch: field pool generated in {time.perf_counter() - t0:.1f} s")
+    imgs, flds, outs_b, outs_s = [], [], [], []
+    for s in sides:
+        r0, c0 = rng.integers(0, H - s + 1), rng.integers(0, W - s + 1)
+        fr, fc = rng.integers(0, 2048 - s + 1), rng.integers(0, 2048 - s + 1)
+        imgs.append(img_dev[r0:r0 + s, c0:c0 + s])
+        flds.append(pool[fr:fr + s, fc:fc + s])
+        outs_b.append(torch.empty((s, s), dtype=torch.float32, device=dev))
+        outs_s.append(torch.empty((s, s), dtype=torch.float32, device=dev))
+    px = int(sum(int(s) * int(s) for s in sides))
+    o = P.default_opts()
+    im_d = [P.image_of(t) for t in imgs]
+    fl_d = [P.field_of(t, P.SVF_FIELD_SRT3) for t in flds]
+    ob_d = [P.image_of(t) for t in outs_b]
+    os_d = [P.image_of(t) for t in outs_s]
+    stream = torch.cuda.Stream()
+
+    def run_batch():
+        P.svf_filter_batch(ctx, im_d, fl_d, [ORDER] * 64, o, ob_d, stream, True)
+
+    def run_single():
+        for i in range(64):
+            P.svf_filter(ctx, im_d[i], fl_d[i], 4, ORDER, o, os_d[i], stream)
+
+    res = {}
+    for name, fn in (("graph_batch", run_batch), ("per_image", run_single)):
+        for _ in range(2):
+            fn()
+        stream.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        stream.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        res[name] = {"ms": round(ms, 3), "Mpixel_s": round(px / (ms * 1e-3) / 1e6, 1)}
+    diff = 0.0
+    for a, b in zip(outs_b, outs_s):
+        a64, b64 = a.double(), b.double()
+        scale = torch.clamp(b64.abs(), min=1e-3 * float(b64.abs().max()))
+        diff = max(diff, float(((a64 - b64).abs() / scale).max()))
+    res.update({
+        "workload": "64 FP32 images, sides uniform from {256,512,1024,2048}, ZP order 2, own smooth fields "
+                    "(sigma 1-16 px, rho 1-4, corr. 64 px), f64 pre-integration",
+        "pixels": px,
+        "speedup": round(res["per_image"]["ms"] / res["graph_batch"]["ms"], 3),
+        "max_rel_diff_batch_vs_per_image": diff,
+    })
+    log(f"batch: graph {res['graph_batch']['ms']:.2f} ms, per-image {res['per_image']['ms']:.2f} ms, "
+        f"max rel diff {diff:.1e}")
+    return res
+
+
+# ----------------------------------------------------------------------------- serving leg
+
+def serving_requests(rng, n):
+    reqs = []
+    for _ in range(n):
+        L = int(rng.integers(512, 4097))
+        S = max(1, int(round(L / rng.uniform(1.0, 2.0))))
+        h, w = (L, S) if rng.random() < 0.5 else (S, L)
+        r0, c0 = int(rng.integers(0, H - h + 1)), int(rng.integers(0, W - w + 1))
+        reqs.append((h, w, r0, c0, int(rng.integers(1, 4))))
+    return reqs
+
+
+def pct(v, q):
+    return round(float(np.percentile(np.asarray(v), q)) * 1e3, 3) if len(v) else None
+
+
+def serve_server(P, ctx, img3, fld, reqs, arrivals, torch):
+    """Submit at the arrival times; returns per-request latency from arrival (s) and the makespan."""
+    dev = img3.device
+    cfg = P.svf_server_cfg()
+    cfg.max_inflight = 16
+    cfg.queue_capacity = len(reqs) + 16
+    cfg.hbm_budget_bytes = 48 << 30
+    cfg.opts = P.default_opts()
+    P.svf_server_start(ctx, cfg)
+    lat, done_t, pending = {}, {}, collections.deque()
+    try:
+        t0 = time.perf_counter()
+
+        def retire(block=False):
+            while pending:
+                rid, _out, i = pending[0]
+                r = P.svf_server_wait(ctx, rid, 60.0) if block else P.svf_server_poll(ctx, rid)
+                if not r.done:
+                    return
+                if r.status != P.SVF_OK:
+                    raise RuntimeError(f"request {i} failed: status {r.status}")
+                done_t[i] = r.t_done_us * 1e-6 - t0
+                lat[i] = done_t[i] - arrivals[i]
+                pending.popleft()
+
+        for i, (h, w, r0, c0, order) in enumerate(reqs):
+            while True:
+                now = time.perf_counter() - t0
+                if now >= arrivals[i]:
+                    break
+                retire()
+                time.sleep(min(2e-4, arrivals[i] - now))
+            out = torch.empty((h, w, 3), dtype=torch.float32, device=dev)
+            req = P.server_request(img3[r0:r0 + h, c0:c0 + w], fld[r0:r0 + h, c0:c0 + w], P.SVF_FIELD_SRT3, order, out)
+            pending.append((P.svf_server_submit(ctx, req), out, i))
+        retire(block=True)
+        st = P.svf_server_stats(ctx)
+    finally:
+        P.svf_server_stop(ctx)
+    lats = [lat[i] for i in range(len(reqs))]
+    return lats, max(done_t.values()) - float(arrivals[0]), st
+
+
+def serve_fifo(P, ctx, img3, fld, reqs, arrivals, torch):
+    """One image per launch in arrival order: svf_filter, then wait for it."""
+    dev = img3.device
+    stream = torch.cuda.Stream()
+    o = P.default_opts()
+    lats, last = [], 0.0
+    t0 = time.perf_counter()
+    for i, (h, w, r0, c0, order) in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if now < arrivals[i]:
+            time.sleep(arrivals[i] - now)
+        out = torch.empty((h, w, 3), dtype=torch.float32, device=dev)
+        P.svf_filter(ctx, P.image_of(img3[r0:r0 + h, c0:c0 + w]),
+                     P.field_of(fld[r0:r0 + h, c0:c0 + w], P.SVF_FIELD_SRT3), 4, order, o, P.image_of(out), stream)
+        stream.synchronize()
+        last = time.perf_counter() - t0
+        lats.append(last - arrivals[i])
+    return lats, last - float(arrivals[0])
+
+
+def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, n_sat=120):
+    dev = fld_dev.device
+    t0 = time.perf_counter()
+    img3 = torch.from_numpy(I.uniform_image(H, W, SEED + 5, channels=3)).to(dev)
+    log(f"serving: 3-channel pool generated in {time.perf_counter() - t0:.1f} s")
+    rng = np.random.default_rng(SEED + 5)
+    n = max(1, int(qps * seconds))
+    reqs = serving_requests(rng, n)
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, n))
+    arrivals -= arrivals[0]
+    px = sum(h * w for h, w, *_ in reqs)
+    # warm both paths on the largest shape (workspace growth is not part of a request)
+    big = (4096, 4096, 0, 0, 3)
+    serve_fifo(P, ctx, img3, fld_dev, [big], np.zeros(1), torch)
+    serve_server(P, ctx, img3, fld_dev, [big], np.zeros(1), torch)
+    out = {
+        "workload": f"Poisson arrivals at {qps:g} req/s for {seconds:g} s ({n} requests): 3-channel FP32 images, "
+                    "long side uniform 512-4096 px, aspect 1:1-1:2, order uniform 1-3, own crops of a smooth "
+                    "field (sigma 1-32 px, rho 1-6), f64 pre-integration",
+        "requests": n, "pixels": int(px), "channels": 3,
+    }
+    lat_s, span_s, st = serve_server(P, ctx, img3, fld_dev, reqs, arrivals, torch)
+    lat_f, span_f = serve_fifo(P, ctx, img3, fld_dev, reqs, arrivals, torch)
+    out["server"] = {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "Mpixel_s": round(px / span_s / 1e6, 1),
+                     "steps": int(st.steps)}
+    out["one_image_per_launch"] = {"p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
+                                   "Mpixel_s": round(px / span_f / 1e6, 1)}
+    log(f"serving @ {qps:g} req/s: server p50 {out['server']['p50_ms']} ms p99 {out['server']['p99_ms']} ms; "
+        f"per-launch p50 {out['one_image_per_launch']['p50_ms']} ms p99 {out['one_image_per_launch']['p99_ms']} ms")
+    # saturated: every request present at t = 0
+    sat = reqs[:n_sat]
+    z = np.zeros(len(sat))
+    spx = sum(h * w for h, w, *_ in sat)
+    _, span_s, _ = serve_server(P, ctx, img3, fld_dev, sat, z, torch)
+    _, span_f = serve_fifo(P, ctx, img3, fld_dev, sat, z, torch)
+    out["saturated"] = {"requests": len(sat), "server_Mpixel_s": round(spx / span_s / 1e6, 1),
+                        "one_image_per_launch_Mpixel_s": round(spx / span_f / 1e6, 1)}
+    log(f"saturated: server {out['saturated']['server_Mpixel_s']} Mpx/s, "
+        f"per-launch {out['saturated']['one_image_per_launch_Mpixel_s']} Mpx/s")
+    return out
+
+
+# ----------------------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -68,10 +289,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
     ap.add_argument("--tile", type=int, default=0, help="output tile side (0 = library default)")
+    ap.add_argument("--qps", type=float, default=500.0, help="serving arrival rate (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the filter's multi-GPU sharding "
@@ -108,8 +333,6 @@ def main():
     stream = torch.cuda.current_stream()
 
     st, rep = P.svf_filter(ctx, im_d, fl_d, 4, ORDER, o, out_d, stream, report=True)
-    if st != P.SVF_OK:
-        raise SystemExit(f"svf_filter: {ctx.last_error()}")
     log(f"report: clamped {rep.clamped_px} eps-active {rep.eps_active_px} invalid {rep.invalid_px} "
         f"overflow {rep.overflow_px} max reach {rep.max_reach_px:.1f} px")
     for _ in range(args.warmup):
@@ -135,23 +358,23 @@ def main():
     fd_ms, fd_n = kt["fd"]
     fd_avg_s = fd_ms / max(fd_n, 1) * 1e-3
     achieved = FD_FLOPS_PER_PX * H * W / fd_avg_s / 1e12
+    traffic, traffic_src = fd_traffic_per_launch() if args.preint == "f64" and args.tile == 0 else (None, "other config")
     roofline = {
-        "kernel": "k_fd (16-tap finite difference + ZP interpolation, FP64)",
         "bound": "alu",
         "achieved": round(achieved, 3),
         "peak": FP64_VECTOR_PEAK,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_VECTOR_PEAK, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "kernel": "k_fd (16-tap finite difference + 7-point ZP interpolation, FP64), one launch = one pass "
+                  "over 4096x4096 px",
         "avg_launch_us": round(fd_avg_s * 1e6, 2),
         "algorithmic_flops_per_px": FD_FLOPS_PER_PX,
+        "traffic_source": traffic_src,
+        "kernel_source_sha256_16": kernel_source_hash(),
     }
-    pre_ms, pre_n = kt["preint"]
-    extra = {
-        "hbm_roofline_frac_72Bpx": round(ALGO_BYTES_PER_PX_PASS * ORDER * H * W / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-        "kernel_avg_us": {k: round(tot / max(n, 1) * 1e3, 2) for k, (tot, n) in kt.items()},
-        "report": {"clamped_px": rep.clamped_px, "eps_active_px": rep.eps_active_px, "max_reach_px": round(rep.max_reach_px, 2)},
-    }
+    if traffic:
+        roofline["traffic_GBps"] = round(traffic / fd_avg_s / 1e9, 1)
     line = {
         "metric": METRIC,
         "value": round(mpx_s, 2),
@@ -175,8 +398,15 @@ def main():
             "tile": args.tile or "auto",
         },
         "roofline": roofline,
-        **extra,
+        "hbm_roofline_frac_72Bpx": round(ALGO_BYTES_PER_PX_PASS * ORDER * H * W / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "kernel_avg_us": {k: round(tot / max(n, 1) * 1e3, 2) for k, (tot, n) in kt.items()},
+        "report": {"clamped_px": rep.clamped_px, "eps_active_px": rep.eps_active_px,
+                   "max_reach_px": round(rep.max_reach_px, 2)},
     }
+    if not args.no_batch:
+        line["batch"] = batch_leg(P, I, ctx, ti, torch)
+    if not args.no_serve:
+        line["serving"] = serving_leg(P, I, ctx, tf, torch, args.qps, args.serve_seconds)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3)

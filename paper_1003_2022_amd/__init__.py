@@ -273,3 +273,48 @@ def filter_tensor(ctx: Context, img, field, kind: int, order: int = 1, out=None,
         st, rep = r
         return out, st, rep
     return out
+
+
+# ----------------------------------------------------------------------------- serving loop (same names as the ABI)
+
+def svf_server_start(ctx: Context, cfg: svf_server_cfg):
+    return ctx.check(lib().svf_server_start(ctx.ptr, C.byref(cfg)))
+
+
+def svf_server_submit(ctx: Context, req: svf_request) -> int:
+    """Queue a request; returns its id (raises SvfError with SVF_EBUSY / SVF_ENOMEM when refused)."""
+    rid = C.c_uint64()
+    ctx.check(lib().svf_server_submit(ctx.ptr, C.byref(req), C.byref(rid)))
+    return rid.value
+
+
+def svf_server_poll(ctx: Context, rid: int) -> svf_result:
+    res = svf_result()
+    ctx.check(lib().svf_server_poll(ctx.ptr, C.c_uint64(rid), C.byref(res)))
+    return res
+
+
+def svf_server_wait(ctx: Context, rid: int, timeout_s: float = -1.0) -> svf_result:
+    res = svf_result()
+    ctx.check(lib().svf_server_wait(ctx.ptr, C.c_uint64(rid), C.byref(res), timeout_s))
+    return res
+
+
+def svf_server_stats(ctx: Context) -> svf_server_stats_t:
+    st = svf_server_stats_t()
+    ctx.check(lib().svf_server_stats(ctx.ptr, C.byref(st)))
+    return st
+
+
+def svf_server_stop(ctx: Context):
+    return ctx.check(lib().svf_server_stop(ctx.ptr))
+
+
+def server_request(img, field, kind: int, order: int, out) -> svf_request:
+    """Request descriptor from device tensors (views with row strides are fine)."""
+    r = svf_request()
+    r.in_ = image_of(img)
+    r.field = field_of(field, kind)
+    r.order = order
+    r.out = image_of(out)
+    return r
