@@ -19,9 +19,13 @@ Beside it, in the same JSON line:
                 1:2), orders 1-3: the continuous-batching server against a FIFO
                 of svf_filter calls (one image per launch), p50/p99 latency from
                 arrival, and the saturated throughput of both;
+  precision     each pre-integration variant (FP64, compensated FP32, int64 for
+                uint16 input) and the FP32 finite difference on the same
+                workload: max and RMS relative error against the CPU FP64
+                oracle on sampled regions, and ms per step;
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve] [--no-precision]
                     [--calib-copy] [--preint f64|f32c] [--tile T] [--qps Q] [--serve-seconds S]
 """
 from __future__ import annotations
@@ -281,6 +285,59 @@ def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, n_sat=120):
     return out
 
 
+# ----------------------------------------------------------------------------- precision leg
+
+PREC_REGIONS = [(0, 0, 96, 96), (2000, 2040, 96, 96), (4000, 3990, 96, 106)]
+
+
+def rel_errors(got, ref):
+    """Max and RMS of |got - ref| / max(|ref|, 1e-3 max|ref|) per pixel."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    e = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    return float(e.max()), float(np.sqrt(np.mean(e * e)))
+
+
+def precision_leg(P, I, ctx, img, fld, ti, tf, torch, steps=5):
+    """Every pre-integration variant on the 4096^2 workload, FP32 and uint16 inputs: error vs the oracle, time."""
+    import oracle
+
+    oracle.build()
+    img16 = I.uniform_image(H, W, SEED + 1, dtype="u16")
+    t16 = torch.from_numpy(img16).to(ti.device)
+    refs = {}
+    t0 = time.perf_counter()
+    for name, im in (("f32", img), ("u16", img16)):
+        refs[name] = [oracle.filter_region(im, fld, P.SVF_FIELD_SRT3, ORDER, r) for r in PREC_REGIONS]
+    log(f"precision: oracle regions in {time.perf_counter() - t0:.1f} s")
+    variants = [("f32", "f64", P.SVF_PRE_F64, 0), ("f32", "f32c", P.SVF_PRE_F32C, 0), ("f32", "f64+fd_fp32", P.SVF_PRE_F64, 1),
+                ("u16", "i64", P.SVF_PRE_I64, 0), ("u16", "f64", P.SVF_PRE_F64, 0), ("u16", "f32c", P.SVF_PRE_F32C, 0)]
+    fl_d = P.field_of(tf, P.SVF_FIELD_SRT3)
+    out = torch.empty((H, W), dtype=torch.float32, device=ti.device)
+    stream = torch.cuda.current_stream()
+    res = {"workload": "4096x4096 order 2, same field as the main line; FP32 image (seed 3000) and uint16 image "
+                       f"(seed 3001); errors on {len(PREC_REGIONS)} sampled regions {PREC_REGIONS} vs the CPU FP64 oracle",
+           "variants": []}
+    for src, name, pre, fd32 in variants:
+        o = P.default_opts(preint=pre, fd_fp32=fd32)
+        im_d = P.image_of(ti if src == "f32" else t16)
+        P.svf_filter(ctx, im_d, fl_d, 4, ORDER, o, P.image_of(out), stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            P.svf_filter(ctx, im_d, fl_d, 4, ORDER, o, P.image_of(out), stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / steps
+        o_np = out.cpu().numpy()
+        errs = [rel_errors(o_np[r0:r0 + h, c0:c0 + w], ref) for (r0, c0, h, w), ref in zip(PREC_REGIONS, refs[src])]
+        mx = max(e[0] for e in errs)
+        rms = float(np.sqrt(np.mean([e[1] ** 2 for e in errs])))
+        res["variants"].append({"input": src, "preint": name, "max_rel": mx, "rms_rel": rms, "ms_per_step": round(ms, 3),
+                                "Mpixel_s": round(H * W / (ms * 1e-3) / 1e6, 1)})
+        log(f"precision {src}/{name}: max rel {mx:.2e} rms {rms:.2e}  {ms:.3f} ms/step")
+    return res
+
+
 # ----------------------------------------------------------------------------- main
 
 def main():
@@ -291,6 +348,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-variant leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
@@ -403,6 +461,8 @@ def main():
         "report": {"clamped_px": rep.clamped_px, "eps_active_px": rep.eps_active_px,
                    "max_reach_px": round(rep.max_reach_px, 2)},
     }
+    if not args.no_precision:
+        line["precision"] = precision_leg(P, I, ctx, img, fld, ti, tf, torch)
     if not args.no_batch:
         line["batch"] = batch_leg(P, I, ctx, ti, torch)
     if not args.no_serve:
