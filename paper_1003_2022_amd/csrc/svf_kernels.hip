@@ -714,16 +714,36 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
     const bool live = r < J.H && c < J.W;
     const Window w = window_of(J, tile);
     const int ww = w.w;
-    // anchor: the block's centre pixel (inside the image); region origin per distinct coordinate
+    // Region origins, one per distinct abscissa / ordinate, from the block's centre
+    // pixel: region column = window column - AX, so that a pixel at block offset ox
+    // with the centre's scales lands on column ox + 1 + kRegM.  Lane k < 16 of each
+    // wave computes the centre's coordinate k (abscissa k, or ordinate k - 8) and the
+    // values are read back as uniform registers.
     int AX[8], AY[8];
     {
-        R dxa[8], dya[8], wa;
         const int64_t ra = min(br0 + kFdSide / 2, J.H - 1), ca = min(bc0 + kFdSide / 2, J.W - 1);
-        tap_coords<R>(J, w, ra, ca, dxa, dya, AX, AY, wa);
+        const float4 af = *reinterpret_cast<const float4 *>(J.scales + ra * J.sc_rs + ca * 4);
+        const R m = (R)J.inv_sqrt_m_d;
+        const R a1 = (R)af.x * m, a2 = (R)af.y * m, a3 = (R)af.z * m, a4 = (R)af.w * m;
+        const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
+        const int k = t & 15, b0 = k & 1, b1 = (k >> 1) & 1, b2 = (k >> 2) & 1;
+        R v;
+        if (k < 8) {   // same operations as tap_coords
+            v = (R)(ca - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
+            if (b0) v -= a1;
+            if (b1) v -= ap2;
+            if (b2) v += ap4;
+        } else {
+            v = (R)(ra - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
+            if (b0) v -= ap2;
+            if (b1) v -= a3;
+            if (b2) v -= ap4;
+        }
+        const int iv = min(max((int)rint(v), 1), (k < 8 ? ww : w.h) - 2);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            AX[i] = __builtin_amdgcn_readfirstlane(AX[i]) - (int)(ca - bc0) - 1 - kRegM;
-            AY[i] = __builtin_amdgcn_readfirstlane(AY[i]) - (int)(ra - br0) - 1 - kRegM;
+            AX[i] = __builtin_amdgcn_readlane(iv, i) - (int)(ca - bc0) - 1 - kRegM;
+            AY[i] = __builtin_amdgcn_readlane(iv, 8 + i) - (int)(ra - br0) - 1 - kRegM;
         }
     }
     R DX[8], DY[8], wgt;
@@ -740,15 +760,23 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
             kBufWord3);
     // loads of tap j go to register slot j % kFdPrefetch; tap j is fetched kFdPrefetch
     // taps before it is staged
+    // Region entry e = t + 256 k of tap i is window sample (AY + e / 27) * ww + AX + e % 27:
+    // a fixed per-thread part and a uniform per-tap part.  Entries past kRegN are
+    // loaded and staged but never read.
+    int toff[kRegLoads];
+#pragma unroll
+    for (int k = 0; k < kRegLoads; ++k) {
+        const int e = t + 256 * k;
+        toff[k] = (e / kRegS) * ww + e % kRegS;
+    }
     double pre[kFdPrefetch][NCH][kRegLoads];
     auto fetch = [&](int i) {
         const int xi = (i & 1) + 2 * ((i >> 1) & 1) + 4 * ((i >> 3) & 1);
         const int yi = ((i >> 1) & 1) + 2 * ((i >> 2) & 1) + 4 * ((i >> 3) & 1);
+        const int sb = AY[yi] * ww + AX[xi];   // uniform
 #pragma unroll
         for (int k = 0; k < kRegLoads; ++k) {
-            const int e = t + 256 * k;   // entries past kRegN are loaded and staged but never read
-            const int er = e / kRegS, ec = e - er * kRegS;
-            const uint32_t off = (uint32_t)((AY[yi] + er) * ww + AX[xi] + ec) * 8u;   // negative wraps: OOB -> 0
+            const uint32_t off = (uint32_t)(sb + toff[k]) * 8u;   // negative wraps: OOB -> 0
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) pre[i % kFdPrefetch][ch][k] = gload<PRE>(rs[ch], off);
         }
