@@ -16,9 +16,10 @@ Beside it, in the same JSON line:
                 each with its own field: one graph-replayed batched launch
                 against 64 svf_filter calls;
   serving       Poisson arrivals of 3-channel images 512..4096 px (aspect 1:1 to
-                1:2), orders 1-3: the continuous-batching server against a FIFO
-                of svf_filter calls (one image per launch), p50/p99 latency from
-                arrival, and the saturated throughput of both;
+                1:2), orders 1-3, at two request rates: the continuous-batching
+                server against a FIFO of svf_filter calls (one image per
+                launch), p50/p99 latency from arrival, and the saturated
+                throughput of both;
   precision     each pre-integration variant (FP64, compensated FP32, int64 for
                 uint16 input) and the FP32 finite difference on the same
                 workload: max and RMS relative error against the CPU FP64
@@ -180,13 +181,14 @@ def pct(v, q):
     return round(float(np.percentile(np.asarray(v), q)) * 1e3, 3) if len(v) else None
 
 
-def serve_server(P, ctx, img3, fld, reqs, arrivals, torch):
+def serve_server(P, ctx, img3, fld, reqs, arrivals, torch, step_mpx=0):
     """Submit at the arrival times; returns per-request latency from arrival (s) and the makespan."""
     dev = img3.device
     cfg = P.svf_server_cfg()
     cfg.max_inflight = 16
     cfg.queue_capacity = len(reqs) + 16
     cfg.hbm_budget_bytes = 48 << 30
+    cfg.step_mpixels = step_mpx
     cfg.opts = P.default_opts()
     P.svf_server_start(ctx, cfg)
     lat, done_t, pending = {}, {}, collections.deque()
@@ -243,40 +245,46 @@ def serve_fifo(P, ctx, img3, fld, reqs, arrivals, torch):
     return lats, last - float(arrivals[0])
 
 
-def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, n_sat=120):
+def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, step_mpx=0, n_sat=120):
     dev = fld_dev.device
     t0 = time.perf_counter()
     img3 = torch.from_numpy(I.uniform_image(H, W, SEED + 5, channels=3)).to(dev)
     log(f"serving: 3-channel pool generated in {time.perf_counter() - t0:.1f} s")
     rng = np.random.default_rng(SEED + 5)
-    n = max(1, int(qps * seconds))
+    n = max(1, int(max(qps) * seconds))
     reqs = serving_requests(rng, n)
-    arrivals = np.cumsum(rng.exponential(1.0 / qps, n))
-    arrivals -= arrivals[0]
+    arrivals0 = np.cumsum(rng.exponential(1.0, n))   # unit-rate Poisson process, scaled per load
+    arrivals0 -= arrivals0[0]
     px = sum(h * w for h, w, *_ in reqs)
     # warm both paths on the largest shape (workspace growth is not part of a request)
     big = (4096, 4096, 0, 0, 3)
     serve_fifo(P, ctx, img3, fld_dev, [big], np.zeros(1), torch)
-    serve_server(P, ctx, img3, fld_dev, [big], np.zeros(1), torch)
+    serve_server(P, ctx, img3, fld_dev, [big], np.zeros(1), torch, step_mpx)
     out = {
-        "workload": f"Poisson arrivals at {qps:g} req/s for {seconds:g} s ({n} requests): 3-channel FP32 images, "
+        "workload": f"Poisson arrivals at {'/'.join(f'{q:g}' for q in qps)} req/s ({n} requests): 3-channel FP32 images, "
                     "long side uniform 512-4096 px, aspect 1:1-1:2, order uniform 1-3, own crops of a smooth "
                     "field (sigma 1-32 px, rho 1-6), f64 pre-integration",
         "requests": n, "pixels": int(px), "channels": 3,
+        "server_config": {"max_inflight": 16, "step_mpixels": step_mpx or "default (64)"},
     }
-    lat_s, span_s, st = serve_server(P, ctx, img3, fld_dev, reqs, arrivals, torch)
-    lat_f, span_f = serve_fifo(P, ctx, img3, fld_dev, reqs, arrivals, torch)
-    out["server"] = {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "Mpixel_s": round(px / span_s / 1e6, 1),
-                     "steps": int(st.steps)}
-    out["one_image_per_launch"] = {"p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
-                                   "Mpixel_s": round(px / span_f / 1e6, 1)}
-    log(f"serving @ {qps:g} req/s: server p50 {out['server']['p50_ms']} ms p99 {out['server']['p99_ms']} ms; "
-        f"per-launch p50 {out['one_image_per_launch']['p50_ms']} ms p99 {out['one_image_per_launch']['p99_ms']} ms")
+    out["loads"] = []
+    for q in qps:
+        arr = arrivals0 / q
+        lat_s, span_s, st = serve_server(P, ctx, img3, fld_dev, reqs, arr, torch, step_mpx)
+        lat_f, span_f = serve_fifo(P, ctx, img3, fld_dev, reqs, arr, torch)
+        rec = {"qps": q, "offered_Mpixel_s": round(px / float(arr[-1]) / 1e6, 1),
+               "server": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "Mpixel_s": round(px / span_s / 1e6, 1),
+                          "steps": int(st.steps)},
+               "one_image_per_launch": {"p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
+                                        "Mpixel_s": round(px / span_f / 1e6, 1)}}
+        out["loads"].append(rec)
+        log(f"serving @ {q:g} req/s: server p50 {rec['server']['p50_ms']} ms p99 {rec['server']['p99_ms']} ms; "
+            f"per-launch p50 {rec['one_image_per_launch']['p50_ms']} ms p99 {rec['one_image_per_launch']['p99_ms']} ms")
     # saturated: every request present at t = 0
     sat = reqs[:n_sat]
     z = np.zeros(len(sat))
     spx = sum(h * w for h, w, *_ in sat)
-    _, span_s, _ = serve_server(P, ctx, img3, fld_dev, sat, z, torch)
+    _, span_s, _ = serve_server(P, ctx, img3, fld_dev, sat, z, torch, step_mpx)
     _, span_f = serve_fifo(P, ctx, img3, fld_dev, sat, z, torch)
     out["saturated"] = {"requests": len(sat), "server_Mpixel_s": round(spx / span_s / 1e6, 1),
                         "one_image_per_launch_Mpixel_s": round(spx / span_f / 1e6, 1)}
@@ -353,8 +361,9 @@ def main():
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
     ap.add_argument("--tile", type=int, default=0, help="output tile side (0 = library default)")
-    ap.add_argument("--qps", type=float, default=500.0, help="serving arrival rate (requests/s)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--qps", default="400,600", help="serving arrival rates (requests/s), comma-separated")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="duration of the highest-rate arrival stream")
+    ap.add_argument("--serve-step-mpx", type=int, default=0, help="server work per step (Mpixel x channels, 0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the filter's multi-GPU sharding "
@@ -466,7 +475,8 @@ def main():
     if not args.no_batch:
         line["batch"] = batch_leg(P, I, ctx, ti, torch)
     if not args.no_serve:
-        line["serving"] = serving_leg(P, I, ctx, tf, torch, args.qps, args.serve_seconds)
+        line["serving"] = serving_leg(P, I, ctx, tf, torch, [float(q) for q in args.qps.split(",")], args.serve_seconds,
+                                      args.serve_step_mpx)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3)

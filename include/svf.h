@@ -10,12 +10,12 @@
  *                                                          the Dirac-comb input)
  *
  * realised by Algorithm 1: the running sums RS1..RS4 with lattice scales
- * b = (1, sqrt2, 1, sqrt2) (Sec. 4.1 step (1)), then at every pixel the 16-tap
+ * b = (1, sqrt2, 1, sqrt2) (Sec. 3.1 step (1)), then at every pixel the 16-tap
  * finite difference of eq. (final_eqn) with the taps of Table 1 and the shift
- * tau of Sec. 4.1 step (2), sampling the ZP-interpolated pre-integrated image
+ * tau of Sec. 3.1 step (2), sampling the ZP-interpolated pre-integrated image
  * (App. F).  The per-pixel scale vector a(n) comes from the pixel's covariance
- * by the optimisation of Sec. 4.2.2; order m > 1 runs m passes with a/sqrt(m)
- * (Sec. 4.3).  N (directions) must be 4.
+ * by the optimisation of Sec. 3.2.2; order m > 1 runs m passes with a/sqrt(m)
+ * (Sec. 3.3).  N (directions) must be 4.
  *
  * Conventions (all entry points):
  *  - Images are row-major: sample (row r, column c, channel ch) sits at
@@ -127,12 +127,12 @@ svf_status svf_destroy(svf_ctx *ctx);
 const char *svf_last_error(const svf_ctx *ctx);
 
 /* Device workspace, in bytes, that svf_filter needs for these arguments
- * (Sec. 4.1: one pre-integrated window per output tile and channel, sized by
+ * (Sec. 3.1: one pre-integrated window per output tile and channel, sized by
  * opts->max_reach_px; plus the scale field).  Host-only, no device access. */
 svf_status svf_workspace_bytes(const svf_image *in, int N, int order, const svf_opts *opts, size_t *bytes);
 
 /*
- * Scale-vector map (Sec. 4.2.2, Prop. 4.1): field -> scales of the whole
+ * Scale-vector map (Sec. 3.2.2, Prop. 3.1): field -> scales of the whole
  * filter, float32 (a1, a2, a3, a4) per pixel into scales_out (device, H x W x 4,
  * contiguous).  An infeasible elongation is lowered to the largest feasible one
  * at the same size and orientation; eps is opts->eps_px2 * order.
@@ -141,7 +141,7 @@ svf_status svf_scale_map(svf_ctx *ctx, const svf_field *field, int64_t H, int64_
                          const svf_opts *opts, float *scales_out, hipStream_t stream);
 
 /*
- * Running sums RS1..RS4 (Sec. 4.1 step (1), Algorithm 1 step 2) of channel
+ * Running sums RS1..RS4 (Sec. 3.1 step (1), Algorithm 1 step 2) of channel
  * `channel` of `in`, on the window rows [r0, r0+h) x cols [c0, c0+w) of the
  * lattice (may extend beyond the image: the input is zero there), with zero
  * initial conditions at the window's top, left and right edges.  g_out
@@ -180,11 +180,11 @@ svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_
  * A scheduler thread owned by the context admits requests (images of any size,
  * each with its own field and order) in arrival order while they fit in a
  * device-memory budget and a slot limit, and runs them with continuous
- * batching: every scheduler step enqueues, on the server's own stream, the
- * scale map of the requests admitted since the last step and then ONE pass
- * (pre-integration + finite difference) of every request in flight, all
- * through the batched persistent kernels.  Requests join and leave between
- * steps.  Each request computes exactly what svf_filter computes with the same
+ * batching: every scheduler step enqueues, on the server's own stream, one
+ * pass (pre-integration + finite difference, preceded by the scale map for a
+ * request's first pass) of the requests in flight, oldest first, up to a
+ * per-step work budget, all through the batched persistent kernels.  Requests
+ * join and leave between steps.  Each request computes exactly what svf_filter computes with the same
  * options (opts.tile 0 means 256 here), so its result does not depend on the
  * mix it ran in.  Input, field and output stay in caller-owned device memory
  * that must remain valid until the request is done.  The integer
@@ -195,7 +195,9 @@ typedef struct {
     int32_t max_inflight;       /* requests on the device at once (default 16) */
     int32_t queue_capacity;     /* waiting requests; submit returns SVF_EBUSY beyond (default 1024) */
     uint64_t hbm_budget_bytes;  /* device memory for the windows and scales of requests in flight */
-    int32_t reserved0;
+    int32_t step_mpixels;       /* work per scheduler step: passes are taken in admission order until
+                                   their pixels x channels reach this many million (the oldest always
+                                   runs; later, smaller passes fill what is left); <= 0: 64 */
     int32_t reserved1;
     svf_opts opts;              /* options of every request */
 } svf_server_cfg;

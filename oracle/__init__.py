@@ -9,9 +9,9 @@ What it computes (Chaudhury, Munoz-Barrutia, Unser, "Fast space-variant
 elliptical filtering using box splines"):
 
 * ``boxspline(a, x, y)``, ``zp(x, y)`` -- the four-directional box spline of
-  Sec. 4 (eq. (const) with N = 4) and its special case the ZP element.
-* ``scales(field, kind, order, eps)`` -- the scale-vector solve of Sec. 4.2.2
-  for every pixel, divided by sqrt(order) for the iterated filter of Sec. 4.3.
+  Sec. 3 (eq. (const) with N = 4) and its special case the ZP element.
+* ``scales(field, kind, order, eps)`` -- the scale-vector solve of Sec. 3.2.2
+  for every pixel, divided by sqrt(order) for the iterated filter of Sec. 3.3.
 * ``preint_window_f64`` / ``preint_window_i64`` -- the running sums RS1..RS4
   (Algorithm 1, step 2) on a window.
 * ``filter(...)`` -- order-m space-variant filtering, either with the fast
@@ -109,13 +109,13 @@ def _img_code(x: np.ndarray) -> int:
 # ----------------------------------------------------------------------------- point evaluations
 
 def boxspline(a, x: float, y: float) -> float:
-    """beta^4_a(x, y) (Sec. 3.2.1 eq. (const), N = 4), a = (a1, a2, a3, a4)."""
+    """beta^4_a(x, y) (Sec. 2.2.1 eq. (const), N = 4), a = (a1, a2, a3, a4)."""
     av = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
     return lib().svfo_boxspline(_dp(av), float(x), float(y))
 
 
 def zp(x: float, y: float) -> float:
-    """ZP element beta^4_b, b = (1, sqrt2, 1, sqrt2) (Sec. 4.1)."""
+    """ZP element beta^4_b, b = (1, sqrt2, 1, sqrt2) (Sec. 3.1)."""
     return lib().svfo_zp(float(x), float(y))
 
 
@@ -136,7 +136,7 @@ def table1_tap(a, i: int):
 
 
 def tau(a):
-    """Shift tau of Sec. 4.1 step (2)."""
+    """Shift tau of Sec. 3.1 step (2)."""
     av = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
     t1, t2 = C.c_double(), C.c_double()
     lib().svfo_tau(_dp(av), C.byref(t1), C.byref(t2))
@@ -179,7 +179,7 @@ def scales(field: np.ndarray, kind: int, order: int = 1, eps: float = DEFAULT_EP
     """Per-pass scales (H, W, 4) f64 for a field (H, W, 3|4) float32.
 
     eps is the per-pass floor on a_k^2; the full-filter solve uses order*eps and
-    each pass uses a / sqrt(order) (Sec. 4.3).  Returns (a, stats dict).
+    each pass uses a / sqrt(order) (Sec. 3.3).  Returns (a, stats dict).
     """
     field = np.ascontiguousarray(field, dtype=np.float32)
     H, W = field.shape[:2]
@@ -245,7 +245,7 @@ def _pass(img, fr0, fc0, a_rect, r0, c0, method, tile):
 def filter_scales(img: np.ndarray, a_pass: np.ndarray, order: int = 1, method: str = "fast", tile: int = 32):
     """Order-m filter of a whole single-channel image given per-pass scales (H, W, 4).
 
-    Pass p reads the (binary64) output of pass p-1, zero outside the image (Sec. 4.3).
+    Pass p reads the (binary64) output of pass p-1, zero outside the image (Sec. 3.3).
     """
     H, W = img.shape
     cur = img

@@ -10,30 +10,30 @@
  * fast.  All arithmetic is IEEE binary64 (integer scans: wrapping 64-bit).
  *
  * Contents (paper section / equation each part follows):
- *   1. Radially-uniform box spline beta^4_a(x) for N = 4 (Sec. 3.2.1, eq. (const)):
+ *   1. Radially-uniform box spline beta^4_a(x) for N = 4 (Sec. 2.2.1, eq. (const)):
  *      the density of sum_k T_k a_k u_k, T_k ~ U(-1/2, 1/2), evaluated exactly
  *      as the overlap area of two rectangles divided by a1 a2 a3 a4.
- *      The ZP element is the case a = b = (1, sqrt2, 1, sqrt2) (Sec. 4.1).
- *   2. Scale-vector solve (Sec. 4.2.2): covariance -> p_bar (pivot p4 = 1),
+ *      The ZP element is the case a = b = (1, sqrt2, 1, sqrt2) (Sec. 3.1).
+ *   2. Scale-vector solve (Sec. 3.2.2): covariance -> p_bar (pivot p4 = 1),
  *      [t_l, t_r], the cubic zeta'(t) with the printed coefficients, its real
  *      roots (Cardano / Viete), argmin of the quartic zeta over roots and ends.
  *      Before the solve, an infeasible elongation is lowered to the largest
  *      feasible value at fixed size and orientation (a reading: the paper
- *      states the bound, Prop. 4.1, but not what to do beyond it).
- *   3. Pre-integration by the four running sums RS1..RS4 (Sec. 4.1 step (1),
+ *      states the bound, Prop. 3.1, but not what to do beyond it).
+ *   3. Pre-integration by the four running sums RS1..RS4 (Sec. 3.1 step (1),
  *      Algorithm 1 step 2) over a rectangular window with zero initial
  *      conditions; FP64, and an integer variant without the sqrt2 factors.
  *   4. Local finite difference with ZP interpolation (eq. (final_eqn),
- *      Table 1 taps, shift tau of Sec. 4.1 step (2)); the interpolant
+ *      Table 1 taps, shift tau of Sec. 3.1 step (2)); the interpolant
  *      F(y) = sum_m g[m] ZP(y - m) is evaluated term by term with part 1.
  *   5. One filter pass over a rectangle of outputs: the fast algorithm
  *      (parts 3 + 4 on windows that contain every sample a pixel reads) and the
  *      brute-force direct sum  out[n] = sum_k f[k] beta^4_{a(n)}(n - k)
- *      (eq. (discrete) with the Dirac-comb input model of Sec. 3.2.2).
+ *      (eq. (discrete) with the Dirac-comb input model of Sec. 2.2.2).
  *
  * Coordinates: image f[row][col]; x = column index n1, y = row index n2.
  * Directions theta_k = (k-1) pi/4: u1 = (1,0), u2 = (1,1)/sqrt2, u3 = (0,1),
- * u4 = (-1,1)/sqrt2 (Sec. 4, eq. before (final_eqn)).
+ * u4 = (-1,1)/sqrt2 (Sec. 3, eq. before (final_eqn)).
  */
 #include <math.h>
 #include <stdint.h>
@@ -102,7 +102,7 @@ double svfo_boxspline(const double *a, double x, double y)
     return shoelace(bx, by, n) / (a[0] * a[1] * a[2] * a[3]);
 }
 
-/* ZP element = beta^4_b, b = (1, sqrt2, 1, sqrt2) (Sec. 4.1). */
+/* ZP element = beta^4_b, b = (1, sqrt2, 1, sqrt2) (Sec. 3.1). */
 double svfo_zp(double x, double y)
 {
     const double b[4] = {1.0, SQ2, 1.0, SQ2};
@@ -117,7 +117,7 @@ void svfo_support_halfwidths(const double *a, double *rx, double *ry)
 }
 
 /* ------------------------------------------------------------------------- */
-/* 2. Scale-vector solve (Sec. 4.2.2)                                         */
+/* 2. Scale-vector solve (Sec. 3.2.2)                                         */
 /* ------------------------------------------------------------------------- */
 
 /* zeta(t) = sum_k (p_k + e_k t)^4 + {(p1+t)^2 + (p3+t)^2}{(p2-t)^2 + (p4-t)^2}, e = (1,-1,1,-1). */
@@ -169,7 +169,7 @@ static int cubic_real_roots(double c3, double c2, double c1, double c0, double *
 
 /*
  * Largest feasible elongation at fixed size s and orientation theta (reading of
- * Prop. 4.1 with the floor p >= eps): the system M p = c, p >= eps has a
+ * Prop. 3.1 with the floor p >= eps): the system M p = c, p >= eps has a
  * solution iff C11 - |C12| >= eps/6 and C22 - |C12| >= eps/6.  Each condition is
  * linear in rho after multiplying by (1 + rho)/s.  Returns +inf when unbounded.
  */
@@ -187,7 +187,7 @@ double svfo_rho_max(double s, double theta, double eps)
     return best;
 }
 
-/* Covariance from descriptor D1 via D2 (Sec. 4.2.1). */
+/* Covariance from descriptor D1 via D2 (Sec. 3.2.1). */
 static void cov_from_srt(double s, double rho, double theta, double *C)
 {
     double lmax = s * rho / (1.0 + rho), lmin = s / (1.0 + rho);
@@ -199,7 +199,7 @@ static void cov_from_srt(double s, double rho, double theta, double *C)
 
 /*
  * Scale vector for covariance C (C[0]=C11, C[1]=C12, C[2]=C22), floor eps on p.
- * Steps (i)-(iii) of Sec. 4.2.2.  Returns 0 on success, -1 if the covariance
+ * Steps (i)-(iii) of Sec. 3.2.2.  Returns 0 on success, -1 if the covariance
  * is not positive definite / not finite, 1 if [t_l, t_r] is empty.
  * *eps_active is set when a component of p sits at the floor.
  */
@@ -252,7 +252,7 @@ int svfo_scales_from_cov_feasible(const double *C, double eps, double *a, int *e
 /*
  * Field entry (sigma, rho, theta) -> scales of the full filter.
  * Reading of the field: size s = lambda_max + lambda_min = 2 sigma^2 (so the
- * isotropic case has covariance sigma^2 I, as in Thm. 3.1), rho = elongation,
+ * isotropic case has covariance sigma^2 I, as in Thm. 2.2), rho = elongation,
  * theta = orientation.  The elongation is lowered to the feasible maximum when
  * needed (*clamped = 1), and the size raised to eps/3 if even rho = 1 is not
  * feasible.  eps is the floor on p = a^2 for this (full) solve.
@@ -409,7 +409,7 @@ static void table1_tap(const double *a, int i, double *x1, double *x2, double *s
     *sgn = ((q1 + q2 + q3 + q4) & 1) ? -1.0 : 1.0;
 }
 
-/* Shift tau of Sec. 4.1 step (2). */
+/* Shift tau of Sec. 3.1 step (2). */
 static void tau_of(const double *a, double *t1, double *t2)
 {
     *t1 = (SQ2 * a[0] + a[1] - a[3] - SQ2) / (2.0 * SQ2);

@@ -2,12 +2,12 @@
 // filter (Chaudhury, Munoz-Barrutia, Unser, "Fast space-variant elliptical
 // filtering using box splines").
 //
-//   k_scale_map : per pixel, covariance field -> box scales (Sec. 4.2.2) and, per tile,
+//   k_scale_map : per pixel, covariance field -> box scales (Sec. 3.2.2) and, per tile,
 //                 the support half-widths that size the pre-integration windows.
-//   k_preint    : running sums RS1..RS4 (Sec. 4.1 step (1), Algorithm 1 step 2) of one
+//   k_preint    : running sums RS1..RS4 (Sec. 3.1 step (1), Algorithm 1 step 2) of one
 //                 tile's window, one work-group sweeping the rows top to bottom.
 //   k_fd        : per pixel, the 16-tap finite difference of eq. (final_eqn) (taps of
-//                 Table 1, shift tau of Sec. 4.1 step (2)) on the ZP interpolant of the
+//                 Table 1, shift tau of Sec. 3.1 step (2)) on the ZP interpolant of the
 //                 pre-integrated window (App. F: 7 lattice samples, one of 4 triangles).
 //
 // Lattice: x = column, y = row, directions u1 = (1,0), u2 = (1,1)/sqrt2, u3 = (0,1),
@@ -84,7 +84,7 @@ __device__ __forceinline__ int find_job(const Job *jobs, int n, int idx, int whi
 }
 
 // ---------------------------------------------------------------------------
-// Scale map (Sec. 4.2.2).  All in binary64.
+// Scale map (Sec. 3.2.2).  All in binary64.
 // ---------------------------------------------------------------------------
 
 // d/dt of ||K||^2 along p = pbar + t (1,-1,1,-1), where ||K||^2 = sum p^4 + (p1^2+p3^2)(p2^2+p4^2)
@@ -590,7 +590,7 @@ __device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_
 
 // Tap coordinates of pixel (r, c) in window coordinates: the 8 distinct abscissae
 // (index q1 + 2 q2 + 4 q4) and ordinates (index q2 + 2 q3 + 4 q4) of n + tau - x_i
-// (Table 1: x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 4.1
+// (Table 1: x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 3.1
 // step (2)), rounded to the nearest lattice point (IX, IY) with the remainders (DX, DY).
 template <typename R>
 __device__ __forceinline__ void tap_coords(const Job &J, const Window &w, int64_t r, int64_t c, R *DX, R *DY,

@@ -3,10 +3,11 @@
 // A scheduler thread owns a device arena and its own HIP stream.  Submitted
 // requests wait in a FIFO queue; the head is admitted when a slot is free and
 // its footprint (per-tile records, scales, one window slot per tile and
-// channel) fits in the arena.  Each step enqueues
-//   fill(tile records of the newly admitted) -> scale map(newly admitted)
-//   -> pre-integration(one pass of every request in flight)
-//   -> finite difference(the same pass)
+// channel) fits in the arena.  Each step takes, in admission order, the next
+// pass of the requests in flight while their pixels x channels fit a per-step
+// budget (the oldest always runs, smaller later passes fill the rest), and enqueues
+//   fill(tile records of those starting) -> scale map(those starting)
+//   -> pre-integration(the step's passes) -> finite difference(the same passes)
 // through the persistent batched kernels, with the descriptor tables staged in
 // pinned memory and uploaded on the server stream (two table sets, alternating).
 // A request at pass p in step k is at pass p+1 in step k+1; a request whose last
@@ -113,6 +114,7 @@ struct Server {
     unsigned char *arena_base = nullptr;
     Arena arena;
     int cap = 0;                       // jobs per table
+    int64_t step_px = 0;               // work budget of one step (pixels x channels)
     StepBuf buf[2];
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -201,10 +203,16 @@ void loop(Server *S)
                 S->inflight.push_back(S->queue.front());
                 S->queue.pop_front();
             }
-            // requests in flight with a pass still to run
+            // this step's work: passes of the requests in flight in admission order while
+            // they fit the budget (the oldest always runs; smaller later ones fill the rest)
+            int64_t used = 0;
             for (uint64_t id : S->inflight) {
                 Req &q = S->reqs[id];
-                if (q.pass < q.r.order) running.emplace_back(id, &q);
+                if (q.pass >= q.r.order) continue;
+                const int64_t px = q.r.in.H * q.r.in.W * q.r.in.channels;
+                if (!running.empty() && used + px > S->step_px) continue;
+                running.emplace_back(id, &q);
+                used += px;
             }
             if (running.empty()) {
                 StepBuf &o = S->buf[(k + 1) & 1];
@@ -295,6 +303,7 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
     S->ctx = ctx;
     S->cfg = c;
     S->cap = c.max_inflight;
+    S->step_px = (int64_t)(c.step_mpixels > 0 ? c.step_mpixels : 64) * 1000000;
     hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&S->arena_base, c.hbm_budget_bytes);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {

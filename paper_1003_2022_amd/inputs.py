@@ -5,13 +5,13 @@ parameter fields.  It contains none of the filter's arithmetic (no covariance
 to scale mapping, no running sums, no finite differences), so it can feed both
 the GPU path and the CPU oracle without coupling them.
 
-Workloads follow the paper's experiments (Sec. 5.1, Table 2: a 512x512 image
+Workloads follow the paper's experiments (Sec. 4.1, Table 2: a 512x512 image
 filtered with kernels of several sizes) and the build's parity/bench configs:
 
 * images: FP32 uniform [0, 1) or uint16 uniform {0..65535};
 * fields: per-pixel (sigma, rho, theta) with sigma = isotropic standard
   deviation in pixels, rho = elongation (variance ratio lambda_max/lambda_min,
-  Sec. 3.2.2 descriptor D1), theta = orientation of the major axis in [0, pi),
+  Sec. 3.2.1 descriptor D1), theta = orientation of the major axis in [0, pi),
   measured from +x (column axis) toward +y (row axis).  Each parameter is a
   Gaussian-smoothed white-noise field mapped to [0, 1) by its empirical CDF.
 """

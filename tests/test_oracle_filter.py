@@ -1,16 +1,16 @@
 """Pins of the oracle's running sums and filter.
 
 * Running sums (Algorithm 1, step 2): the nested infinite sums RS1..RS4 of
-  Sec. 4.1 evaluated by brute force on tiny windows; backward unit differences
+  Sec. 3.1 evaluated by brute force on tiny windows; backward unit differences
   along v4, v3, v2, v1 undo them exactly (integer variant); FP64 = 2 x integer.
 * Taps and shift: Table 1 and the printed tau.
 * Filter: the fast algorithm equals the direct sum sum_k f[k] beta_{a(n)}(n-k)
-  (the exactness of Prop. (link2) with the Dirac-comb input); the direct sum with
+  (the exactness of Prop. 2.1 (link2) with the Dirac-comb input); the direct sum with
   a constant field is an ordinary 2-D convolution (scipy.signal.convolve2d);
   a = b reduces to the ZP lattice stencil 1/2, 1/8; unit mass holds exactly
   when a1, a3 are integers and otherwise equals the Poisson sum of the Fourier
   form prod sinc(a_k u_k.w/2) over w in 2 pi Z^2; iterating m passes with a/sqrt m
-  approaches the Gaussian of the same covariance (Sec. 4.3).
+  approaches the Gaussian of the same covariance (Sec. 3.3).
 """
 import math
 

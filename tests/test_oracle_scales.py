@@ -1,7 +1,7 @@
-"""Pins of the oracle's scale-vector solve (Sec. 4.2.2) against what the paper
+"""Pins of the oracle's scale-vector solve (Sec. 3.2.2) against what the paper
 and the mathematics fix:
 
-* Thm. 3.1 with N = 4: covariance sigma^2 I gives a_k = sigma sqrt6;
+* Thm. 2.2 with N = 4: covariance sigma^2 I gives a_k = sigma sqrt6;
 * the covariance of the solved box spline equals the requested covariance,
   checked with quadrature of the oracle's own box spline (independent of the
   solver's matrix M) and, over many random cases, with eq. (covariance_ZP),
@@ -10,7 +10,7 @@ and the mathematics fix:
 * rotation by pi/4 permutes the scales, (a1,a2,a3,a4) -> (a4,a1,a2,a3)
   (a rotation moves box k onto direction k+1; ||K|| is rotation invariant,
   App. D), which pins every index of the solve;
-* the elongation bound of Prop. 4.1 (eq. (bound)) and its value 3 + 2 sqrt2 at
+* the elongation bound of Prop. 3.1 (eq. (bound)) and its value 3 + 2 sqrt2 at
   the mid-way orientations.
 """
 import math
@@ -39,7 +39,7 @@ def kurt_norm2(p):
 
 
 def U_bound(phi):
-    # Prop. 4.1, eq. (bound)
+    # Prop. 3.1, eq. (bound)
     nu = 0.5 * (math.tan(phi) - 1 / math.tan(phi)) * np.sign(math.pi / 2 - phi)
     r = math.sqrt(1 + nu * nu)
     return (1 + abs(nu) + r) / (1 + abs(nu) - r)
@@ -126,7 +126,7 @@ def test_rotation_by_quarter_pi_permutes_scales(orc):
 
 
 def test_elongation_bound(orc, paper):
-    # eps -> 0: the largest feasible elongation is the bound U(phi) of Prop. 4.1
+    # eps -> 0: the largest feasible elongation is the bound U(phi) of Prop. 3.1
     for phi in np.linspace(0.05, math.pi - 0.05, 57):
         if min(abs(phi - k * math.pi / 4) for k in range(5)) < 1e-3:
             continue
@@ -162,7 +162,7 @@ def test_cov_entry_matches_srt_entry(orc):
 
 def test_printed_zeta_prime_coefficients(orc):
     """The argmin found with the printed cubic agrees with a direct minimisation of
-    ||K||^2 along the line, so the printed coefficients (Sec. 4.2.2) are the derivative."""
+    ||K||^2 along the line, so the printed coefficients (Sec. 3.2.2) are the derivative."""
     rng = np.random.default_rng(8)
     for _ in range(50):
         sigma, theta, rho = 1 + 3 * rng.random(), math.pi * rng.random(), 1 + 1.5 * rng.random()
