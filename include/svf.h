@@ -100,6 +100,12 @@ typedef struct {
                              else 64, 128 or 256 */
     int32_t max_reach_px; /* largest support half-width of one pass the workspace is sized for
                              (default 128 px; <= 380) */
+    int32_t bands;        /* svf_filter: 0 or 1 = whole-image launches in sequence on the caller's
+                             stream (default); 2..8 = that many bands of tile rows (at least 4
+                             tile rows each) on internal streams, pass p of a band starting once
+                             pass p-1 of the bands its windows reach is done.  Results are the
+                             same bit for bit. */
+    int32_t reserved;
 } svf_opts;
 
 typedef struct {

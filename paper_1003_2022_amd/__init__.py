@@ -37,7 +37,7 @@ class svf_field(C.Structure):
 
 class svf_opts(C.Structure):
     _fields_ = [("preint", C.c_int32), ("fd_fp32", C.c_int32), ("eps_px2", C.c_double), ("tile", C.c_int32),
-                ("max_reach_px", C.c_int32)]
+                ("max_reach_px", C.c_int32), ("bands", C.c_int32), ("reserved", C.c_int32)]
 
 
 class svf_report(C.Structure):

@@ -60,6 +60,8 @@ struct Job {
     double eps_full;         // floor on a^2 of the whole filter (order * eps per pass)
     // batched launches: first global tile / FD block / scale block of this job
     int32_t tile_base, blk_base, smap_base, pad0;
+    // single-image launches cover the tile rows [tr0, tr1) (scale map: their pixel rows)
+    int32_t tr0, tr1;
 };
 
 // Rectangle of lattice samples pre-integrated for one tile.

@@ -14,6 +14,7 @@
 // u4 = (-1,1)/sqrt2; the running sums step by b_k u_k = (1,0), (1,1), (0,1), (-1,1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "svf_internal.h"
@@ -287,7 +288,9 @@ __device__ void scale_map_block(const Job &J, int lb)
 
 __global__ __launch_bounds__(256) void k_scale_map(Job J)
 {
-    scale_map_block(J, blockIdx.x);
+    // blocks of 16 pixel rows; the launch starts at the first row of tile row tr0
+    const int nbx = (int)((J.W + kSmapCols - 1) / kSmapCols);
+    scale_map_block(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
 }
 
 __global__ __launch_bounds__(256) void k_scale_map_batch(const Job *jobs, int n, int total)
@@ -513,7 +516,8 @@ template <class A, int IN, int KC>
 __global__ __launch_bounds__(kScanThreads) void k_preint(Job J)
 {
     __shared__ ScanLds<A, KC> L;
-    const int tile = blockIdx.x / J.C, ch = blockIdx.x - tile * J.C;
+    const int lt = blockIdx.x / J.C, ch = blockIdx.x - lt * J.C;
+    const int tile = J.tr0 * J.ntc + lt;
     const Window w = window_of(J, tile);
     void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
     sweep_window<A, IN, KC>(J, ch, w, gout, L);
@@ -833,7 +837,8 @@ __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
 {
     __shared__ double lds[2][NCH][kRegPad];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    if (lb < nblocks) fd_block<PRE, NCH, R>(J, lb, lds);
+    const int bpt = (J.T / kFdSide) * (J.T / kFdSide);
+    if (lb < nblocks) fd_block<PRE, NCH, R>(J, J.tr0 * J.ntc * bpt + lb, lds);
 }
 
 // one work-group per 16 x 16 block of any image of the table (all with NCH channels)
@@ -861,8 +866,8 @@ hipError_t launch_preint_kc(const Job &j, int nb, hipStream_t s)
 template <class A>
 hipError_t launch_preint_t(const Job &j, hipStream_t s)
 {
-    const int nb = j.ntr * j.ntc * j.C;
-    if (nb == 0) return hipSuccess;
+    const int nb = (j.tr1 - j.tr0) * j.ntc * j.C;
+    if (nb <= 0) return hipSuccess;
     switch (chunks_for(j.T, j.cap)) {
     case 1: return launch_preint_kc<A, 1>(j, nb, s);
     case 2: return launch_preint_kc<A, 2>(j, nb, s);
@@ -904,8 +909,9 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
 
 hipError_t launch_scale_map(const Job &j, hipStream_t s)
 {
-    const int nb = scale_map_blocks(j.H, j.W);
-    if (nb == 0) return hipSuccess;
+    const int64_t r0 = (int64_t)j.tr0 * j.T, r1 = std::min((int64_t)j.tr1 * j.T, j.H);
+    if (r1 <= r0) return hipSuccess;
+    const int nb = scale_map_blocks(r1 - r0, j.W);
     hipLaunchKernelGGL(k_scale_map, dim3(nb), dim3(256), 0, s, j);
     return hipGetLastError();
 }
@@ -960,8 +966,8 @@ static hipError_t launch_fd_pr(const Job &j, int nb, int grid, hipStream_t s)
 
 hipError_t launch_fd(const Job &j, hipStream_t s)
 {
-    const int nb = fd_blocks_job(j);
-    if (nb == 0) return hipSuccess;
+    const int nb = (j.tr1 - j.tr0) * j.ntc * (j.T / kFdSide) * (j.T / kFdSide);
+    if (nb <= 0) return hipSuccess;
     const int grid = (nb + 7) / 8 * 8;
     if (j.fd_fp32) {
         switch (j.preint) {

@@ -78,6 +78,8 @@ svf_status check_opts(svf_ctx *ctx, const svf_opts *o, int T)
     const int capmax = (kMaxWindow - T - 5) / 2;
     if (o->max_reach_px < 1 || o->max_reach_px > capmax)
         return fail(ctx, SVF_EINVAL, "opts.max_reach_px must be in [1, %d] for tile %d", capmax, T);
+    if (o->bands < 0 || o->bands > svf_ctx::kMaxBands)
+        return fail(ctx, SVF_EINVAL, "opts.bands must be in [0, %d]", svf_ctx::kMaxBands);
     return SVF_OK;
 }
 
@@ -121,8 +123,9 @@ Plan plan_for(const svf_image *in, int order, const svf_opts *o)
     p.off_tstat = 0;
     p.off_scales = align_up((size_t)p.ntr * p.ntc * sizeof(TileStat), 256);
     p.off_g = align_up(p.off_scales + (size_t)in->H * in->W * 4 * sizeof(float), 256);
-    p.bytes = p.off_g + (size_t)p.ntr * p.ntc * in->channels * p.slot * 8;
-    (void)order;
+    // second pass buffer: pass outputs alternate between it and the caller's output
+    p.off_tmp = align_up(p.off_g + (size_t)p.ntr * p.ntc * in->channels * p.slot * 8, 256);
+    p.bytes = p.off_tmp + (order > 1 ? (size_t)in->H * in->W * in->channels * sizeof(float) : 0);
     return p;
 }
 
@@ -177,6 +180,35 @@ void fill_report(const TileStat *ts, size_t nt, int order, svf_report *rep)
 }
 
 // Fill the parts of a job common to every pass.
+// Bands of tile rows for svf_filter.  Automatic is one band: on the 4096^2
+// workload 2, 4 and 8 concurrent bands measured 3-15 % slower than whole-image
+// launches in sequence (the pre-integration is latency-bound per window however
+// many windows a launch holds, and concurrent kernels slow the issue-bound
+// difference).  Each band is at least 4 tile rows, so that a window reaches only
+// into the next band.
+int pick_bands(const Plan &p, int requested)
+{
+    if (requested <= 1) return 1;
+    return std::min(std::min(requested, svf_ctx::kMaxBands), std::max(1, p.ntr / 4));
+}
+
+svf_status ensure_bands(svf_ctx *ctx, int nb, int order)
+{
+    for (int b = 0; b < nb; ++b) {
+        if (ctx->band_stream[b]) continue;
+        hipError_t e = hipStreamCreateWithFlags(&ctx->band_stream[b], hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamCreateWithFlags");
+    }
+    const size_t need = 1 + (size_t)order * svf_ctx::kMaxBands;
+    while (ctx->band_events.size() < need) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreateWithFlags");
+        ctx->band_events.push_back(ev);
+    }
+    return SVF_OK;
+}
+
 Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
              unsigned char *ws)
 {
@@ -210,6 +242,8 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
     j.fd_fp32 = o->fd_fp32 ? 1 : 0;
     j.eps_full = o->eps_px2 * order;
     j.preint = o->preint;
+    j.tr0 = 0;
+    j.tr1 = p.ntr;
     return j;
 }
 
@@ -279,6 +313,9 @@ svf_status svf_destroy(svf_ctx *ctx)
         hipEventDestroy(p.b);
     }
     for (auto e : ctx->pool) hipEventDestroy(e);
+    for (auto e : ctx->band_events) hipEventDestroy(e);
+    for (auto s : ctx->band_stream)
+        if (s) hipStreamDestroy(s);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
     delete ctx;
@@ -404,20 +441,81 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
 
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(p.off_scales / 4), stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "fill");
-    e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(j, stream); });
-    if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
-    for (int pass = 0; pass < order; ++pass) {
+
+    // Pass outputs alternate between the caller's output and the second pass
+    // buffer so that the last pass lands in the output and no pass writes what
+    // another band may still be reading.
+    float *tmp = reinterpret_cast<float *>(ws + p.off_tmp);
+    auto pass_out = [&](int pass) { return ((order - 1 - pass) % 2 == 0) ? static_cast<float *>(out->data) : tmp; };
+    auto pass_out_rs = [&](int pass) { return ((order - 1 - pass) % 2 == 0) ? out->row_stride : in->W * in->channels; };
+    auto pass_job = [&](int pass, int tr0, int tr1) {
         Job jp = j;
-        if (pass > 0) {   // later passes read the previous output (float32), in place
-            jp.in = out->data;
-            jp.in_rs = out->row_stride;
+        jp.tr0 = tr0;
+        jp.tr1 = tr1;
+        jp.out = pass_out(pass);
+        jp.out_rs = pass_out_rs(pass);
+        if (pass > 0) {   // later passes read the previous pass's float32 output
+            jp.in = pass_out(pass - 1);
+            jp.in_rs = pass_out_rs(pass - 1);
             jp.in_type = kInF32;
             if (jp.preint == kPreI64) jp.preint = kPreF64;
         }
-        e = timed_launch(ctx, kClsPreint, stream, [&] { return launch_preint(jp, stream); });
-        if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
-        e = timed_launch(ctx, kClsFd, stream, [&] { return launch_fd(jp, stream); });
-        if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
+        return jp;
+    };
+
+    const int nb = pick_bands(p, o.bands);
+    if (nb <= 1) {
+        e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(pass_job(0, 0, p.ntr), stream); });
+        if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+        for (int pass = 0; pass < order; ++pass) {
+            const Job jp = pass_job(pass, 0, p.ntr);
+            e = timed_launch(ctx, kClsPreint, stream, [&] { return launch_preint(jp, stream); });
+            if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
+            e = timed_launch(ctx, kClsFd, stream, [&] { return launch_fd(jp, stream); });
+            if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
+        }
+    } else {
+        // Bands of tile rows on internal streams.  Pass p of band b reads pass p-1's
+        // output on its windows, which reach at most cap + 5 rows beyond the band:
+        // it waits for pass p-1 of every band those rows touch.
+        st = ensure_bands(ctx, nb, order);
+        if (st) return st;
+        std::vector<int> tr(nb + 1);
+        for (int b = 0; b <= nb; ++b) tr[b] = (int)((int64_t)p.ntr * b / nb);
+        const int64_t halo = (int64_t)p.cap + 5;
+        auto ev = [&](int pass, int b) { return ctx->band_events[1 + pass * svf_ctx::kMaxBands + b]; };
+        e = hipEventRecord(ctx->band_events[0], stream);
+        for (int b = 0; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(ctx->band_stream[b], ctx->band_events[0], 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "band fork");
+        for (int b = 0; b < nb; ++b) {
+            hipStream_t sb = ctx->band_stream[b];
+            e = timed_launch(ctx, kClsScaleMap, sb, [&] { return launch_scale_map(pass_job(0, tr[b], tr[b + 1]), sb); });
+            if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+        }
+        for (int pass = 0; pass < order; ++pass) {
+            for (int b = 0; b < nb; ++b) {
+                hipStream_t sb = ctx->band_stream[b];
+                if (pass > 0) {
+                    const int64_t lo = (int64_t)tr[b] * p.T - halo, hi = (int64_t)tr[b + 1] * p.T + halo;
+                    for (int o2 = 0; o2 < nb; ++o2) {
+                        if (o2 == b || (int64_t)tr[o2 + 1] * p.T <= lo || (int64_t)tr[o2] * p.T >= hi) continue;
+                        e = hipStreamWaitEvent(sb, ev(pass - 1, o2), 0);
+                        if (e != hipSuccess) return hip_fail(ctx, e, "band dependency");
+                    }
+                }
+                const Job jp = pass_job(pass, tr[b], tr[b + 1]);
+                e = timed_launch(ctx, kClsPreint, sb, [&] { return launch_preint(jp, sb); });
+                if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
+                e = timed_launch(ctx, kClsFd, sb, [&] { return launch_fd(jp, sb); });
+                if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
+                e = hipEventRecord(ev(pass, b), sb);
+                if (e != hipSuccess) return hip_fail(ctx, e, "band event");
+            }
+        }
+        for (int b = 0; b < nb; ++b) {   // join: the caller's stream waits for every band
+            e = hipStreamWaitEvent(stream, ev(order - 1, b), 0);
+            if (e != hipSuccess) return hip_fail(ctx, e, "band join");
+        }
     }
     if (rep) {
         const size_t nt = (size_t)p.ntr * p.ntc;

@@ -33,6 +33,10 @@ struct svf_ctx {
     int64_t count[kNumKernelClasses] = {};
     void *batch = nullptr;             // svf::BatchState
     void *server = nullptr;            // serving loop (svf_server.cpp)
+    // banded svf_filter: internal streams (default priority) and ordering events
+    static constexpr int kMaxBands = 8;
+    hipStream_t band_stream[kMaxBands] = {};
+    std::vector<hipEvent_t> band_events;   // [0]: fork; then pass * kMaxBands + band
     hipEvent_t take_event();
 };
 
@@ -41,7 +45,7 @@ namespace svf {
 struct Plan {
     int T = 0, cap = 0, ntr = 0, ntc = 0;
     int64_t slot = 0;
-    size_t off_tstat = 0, off_scales = 0, off_g = 0, bytes = 0;
+    size_t off_tstat = 0, off_scales = 0, off_g = 0, off_tmp = 0, bytes = 0;
 };
 
 svf_status fail(svf_ctx *ctx, svf_status st, const char *fmt, ...);

@@ -345,7 +345,7 @@ svf_status svf_server_submit(svf_ctx *ctx, const svf_request *req, uint64_t *id)
     Req q;
     q.r = *req;
     q.plan = plan_for(&req->in, req->order, &S->cfg.opts);
-    q.bytes = q.plan.bytes;
+    q.bytes = q.plan.off_tmp;   // passes run in place here: no second pass buffer
     q.t_submit = now_us();
     std::lock_guard<std::mutex> lk(S->mu);
     S->stats.submitted++;

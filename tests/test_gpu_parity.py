@@ -214,3 +214,28 @@ def test_errors(ctx):
     e = torch.empty((0, 7), dtype=torch.float32, device=DEV)
     ef = torch.empty((0, 7, 3), dtype=torch.float32, device=DEV)
     P.svf_filter(ctx, P.image_of(e), P.field_of(ef, P.SVF_FIELD_SRT3), 4, 1, o, P.image_of(e))
+
+
+# ----------------------------------------------------------------------------- banded execution
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_bands_bitwise_equal_to_one_band(ctx, order):
+    # 2048 x 1536 with 64-px tiles: 32 tile rows, enough for 8 bands; pass outputs
+    # alternate between the output and the second buffer, bands wait on neighbours
+    H, W = 2048, 1536
+    img = I.uniform_image(H, W, 3070, channels=2)
+    fld = I.srt_field(H, W, 3070, (1.0, 24.0), (1.0, 6.0), corr_len=96.0)
+    ti, tf = to_dev(img), to_dev(fld)
+    outs = {}
+    for bands in (1, 2, 3, 8):
+        out = torch.full(ti.shape, float("nan"), dtype=torch.float32, device=DEV)
+        P.svf_filter(ctx, P.image_of(ti), P.field_of(tf, P.SVF_FIELD_SRT3), 4, order,
+                     P.default_opts(tile=64, bands=bands), P.image_of(out))
+        torch.cuda.synchronize()
+        outs[bands] = out.cpu().numpy()
+        assert np.isfinite(outs[bands]).all()
+    for bands in (2, 3, 8):
+        assert np.array_equal(outs[bands], outs[1]), f"bands={bands} differs from one band"
+    r = (1000, 700, 96, 80)   # straddles a band boundary; channel 1
+    ref = oracle.filter_region(img[..., 1], fld, oracle.FIELD_SRT3, order, r)
+    check_close(outs[8][r[0]:r[0] + r[2], r[1]:r[1] + r[3], 1], ref, what=f"bands order {order}")
