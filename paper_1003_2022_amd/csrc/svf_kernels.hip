@@ -88,6 +88,29 @@ __device__ __forceinline__ int find_job(const Job *jobs, int n, int idx, int whi
 // Scale map (Sec. 3.2.2).  All in binary64.
 // ---------------------------------------------------------------------------
 
+// Quotient and square root for positive, finite binary64 operands: the hardware
+// estimates (about 2^-23 relative) refined by Newton / Goldschmidt steps to about
+// 1e-15 relative.  Enough for scales that are stored in binary32, and a fraction
+// of the cost of the correctly rounded library sequences.
+__device__ __forceinline__ double div_pos(double a, double b)   // b > 0
+{
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(r, fma(-b, r, 1.0), r);
+    r = fma(r, fma(-b, r, 1.0), r);
+    const double q = a * r;
+    return fma(r, fma(-b, q, a), q);
+}
+
+__device__ __forceinline__ double sqrt_pos(double x)   // x > 0
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(fma(-g, g, x), h, g);
+}
+
 // d/dt of ||K||^2 along p = pbar + t (1,-1,1,-1), where ||K||^2 = sum p^4 + (p1^2+p3^2)(p2^2+p4^2)
 // (App. E), and its second derivative.  Evaluated from the shifted components, not
 // from expanded coefficients.
@@ -124,11 +147,11 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
         t = hi;
     } else {
         const double tol = 1e-13 * fmax(fmax(fabs(pb[0]), fabs(pb[1])), fmax(fabs(pb[2]), 1.0));
-        t = lo + (hi - lo) * (-dlo / (dhi - dlo));
+        t = lo + (hi - lo) * div_pos(-dlo, dhi - dlo);
         for (int it = 0; it < 60; ++it) {
             double d1, d2;
             kurt_d(pb, t, d1, d2);
-            const double step = d1 / d2;
+            const double step = div_pos(d1, d2);   // d2 >= 8 sum p^2 > 0
             // converged: take the last (sub-tolerance) step; tested before the bracket
             // update, since a step below one ulp of t would otherwise read as leaving
             // the bracket and restart bisection from its far end
@@ -146,7 +169,7 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
         double v = p[k];
         if (v <= eps * (1.0 + 1e-12)) eps_act = true;
         v = fmax(v, eps);
-        a[k] = sqrt(v);
+        a[k] = sqrt_pos(v);
     }
 }
 
@@ -155,11 +178,11 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
 // inequalities in rho (multiply by (1 + rho) / s).
 __device__ __forceinline__ double rho_limit(double s, double c, double sn, double eps)
 {
-    const double cs = fabs(c * sn), e = eps / (6.0 * s);
+    const double cs = fabs(c * sn), e = div_pos(eps, 6.0 * s);
     double lim = INFINITY;
     const double k1 = c * c - cs - e, k2 = sn * sn - cs - e;
-    if (k1 < 0.0) lim = fmin(lim, (sn * sn + cs - e) / -k1);
-    if (k2 < 0.0) lim = fmin(lim, (c * c + cs - e) / -k2);
+    if (k1 < 0.0) lim = fmin(lim, div_pos(sn * sn + cs - e, -k1));
+    if (k2 < 0.0) lim = fmin(lim, div_pos(c * c + cs - e, -k2));
     return lim;
 }
 
@@ -174,7 +197,7 @@ __device__ void solve_srt(double sigma, double rho, double th, double eps, doubl
     const double lim = rho_limit(s, c, sn, eps);
     if (rho > lim) { rho = lim * (1.0 - 1e-12); clamped = true; }
     rho = fmax(rho, 1.0);
-    const double lmin = s / (1.0 + rho), dl = lmin * (rho - 1.0);   // lambda_max - lambda_min
+    const double lmin = div_pos(s, 1.0 + rho), dl = lmin * (rho - 1.0);   // lambda_max - lambda_min
     solve_feasible(lmin + dl * c * c, dl * c * sn, lmin + dl * sn * sn, eps, a, eps_act);
 }
 
