@@ -615,46 +615,58 @@ __device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_
     return (double)f.x + (double)f.y;
 }
 
-// Tap coordinates of pixel (r, c) in window coordinates: the 8 distinct abscissae
-// (index q1 + 2 q2 + 4 q4) and ordinates (index q2 + 2 q3 + 4 q4) of n + tau - x_i
-// (Table 1: x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 3.1
-// step (2)), rounded to the nearest lattice point (IX, IY) with the remainders (DX, DY).
+// Abscissae (index q1 + 2 q2 + 4 q4) and ordinates (index q2 + 2 q3 + 4 q4) of the
+// sample positions n + tau - x_i of pixel (r, c), in window coordinates (Table 1:
+// x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 3.1 step (2)).
 template <typename R>
-__device__ __forceinline__ void tap_coords(const Job &J, const Window &w, int64_t r, int64_t c, R *DX, R *DY,
-                                           int *IX, int *IY, R &wgt)
-{
-    const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
-    const R m = (R)J.inv_sqrt_m_d;
-    const R a1 = (R)af.x * m, a2 = (R)af.y * m, a3 = (R)af.z * m, a4 = (R)af.w * m;
-    const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
-    const R cx = (R)(c - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
-    const R cy = (R)(r - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
-    wgt = (R)1 / ((R)8 * a1 * a2 * a3 * a4);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int b0 = i & 1, b1 = (i >> 1) & 1, b2 = (i >> 2) & 1;
-        R x = cx, y = cy;
-        if (b0) x -= a1;     // q1
-        if (b1) x -= ap2;    // q2
-        if (b2) x += ap4;    // q4
-        if (b0) y -= ap2;    // q2
-        if (b1) y -= a3;     // q3
-        if (b2) y -= ap4;    // q4
-        const R rx = rint(x), ry = rint(y);
-        DX[i] = x - rx;
-        DY[i] = y - ry;
-        IX[i] = min(max((int)rx, 1), w.w - 2);
-        IY[i] = min(max((int)ry, 1), w.h - 2);
+struct PixGeom {
+    R a1, ap2, a3, ap4, cx, cy, wgt;   // wgt = 1 / (8 a1 a2 a3 a4): the ZP weights below are 8 x
+    __device__ __forceinline__ PixGeom(const Job &J, const Window &w, int64_t r, int64_t c)
+    {
+        const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
+        const R m = (R)J.inv_sqrt_m_d;
+        a1 = (R)af.x * m;
+        const R a2 = (R)af.y * m;
+        a3 = (R)af.z * m;
+        const R a4 = (R)af.w * m;
+        ap2 = a2 * (R)kRsqrt2;
+        ap4 = a4 * (R)kRsqrt2;
+        cx = (R)(c - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
+        cy = (R)(r - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
+        wgt = (R)1 / ((R)8 * a1 * a2 * a3 * a4);
     }
-}
+    __device__ __forceinline__ R x(int i) const
+    {
+        R v = cx;
+        if (i & 1) v -= a1;    // q1
+        if (i & 2) v -= ap2;   // q2
+        if (i & 4) v += ap4;   // q4
+        return v;
+    }
+    __device__ __forceinline__ R y(int i) const
+    {
+        R v = cy;
+        if (i & 1) v -= ap2;   // q2
+        if (i & 2) v -= a3;    // q3
+        if (i & 4) v -= ap4;   // q4
+        return v;
+    }
+};
+
+// Order of the 16 taps in the difference: four groups of fixed (q2, q4); inside a
+// group (q1, q3) = (0,0), (1,0), (1,1), (0,1), so a group needs two abscissae and two
+// ordinates.
+__host__ __device__ constexpr int step_q1(int k) { return (k & 3) == 1 || (k & 3) == 2; }
+__host__ __device__ constexpr int step_q2(int k) { return (k >> 2) & 1; }
+__host__ __device__ constexpr int step_q3(int k) { return (k & 3) >= 2; }
+__host__ __device__ constexpr int step_q4(int k) { return k >> 3; }
 
 // 8 x the seven ZP weights on the canonical triangle (see above) and the two
 // signed axis steps (oa along the larger remainder component, ob along the other).
 template <typename R>
 struct ZpTap {
     R w00, w10, wm0, w01, w0m, w11, w1m;
-    int sx, sy;
-    bool hz;
+    bool px, py, hz;
     __device__ __forceinline__ ZpTap(R dx, R dy)
     {
         const R adx = fabs(dx), ady = fabs(dy);
@@ -671,13 +683,16 @@ struct ZpTap {
         w0m = A - B;
         w11 = fma((R)4, st, (R)2 * q);
         w1m = fma((R)-4, st, (R)2 * q);
-        sx = dx >= (R)0 ? 1 : -1;
-        sy = dy >= (R)0 ? 1 : -1;
+        px = dx >= (R)0;
+        py = dy >= (R)0;
     }
+    // g(offset in bytes); base: byte offset of the nearest sample, xb / yb: byte steps
+    // of one column / one row
     template <class G>
-    __device__ __forceinline__ R apply(const G &g, int base, int row) const
+    __device__ __forceinline__ R apply(const G &g, int base, int xb, int yb) const
     {
-        const int oa = hz ? sx : sy * row, ob = hz ? sy * row : sx;
+        const int sxb = px ? xb : -xb, syb = py ? yb : -yb;
+        const int oa = hz ? sxb : syb, ob = hz ? syb : sxb;
         R F8 = w00 * (R)g(base);
         F8 = fma(w10, (R)g(base + oa), F8);
         F8 = fma(wm0, (R)g(base - oa), F8);
@@ -719,7 +734,7 @@ __device__ __forceinline__ void fd_direct(const Job &J, const Window &w, int64_t
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const __amdgpu_buffer_rsrc_t rr = rs[ch];
-            const R F8 = z.apply([&](int e) { return gload<PRE>(rr, (uint32_t)e * 8u); }, base, w.w);
+            const R F8 = z.apply([&](int off) { return gload<PRE>(rr, (uint32_t)off); }, base * 8, 8, w.w * 8);
             acc[ch] = ((q1 + q2 + q3 + q4) & 1) ? acc[ch] - F8 : acc[ch] + F8;
         }
     }
@@ -755,7 +770,7 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
         const int k = t & 15, b0 = k & 1, b1 = (k >> 1) & 1, b2 = (k >> 2) & 1;
         R v;
-        if (k < 8) {   // same operations as tap_coords
+        if (k < 8) {   // same operations as PixGeom::x / PixGeom::y
             v = (R)(ca - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
             if (b0) v -= a1;
             if (b1) v -= ap2;
@@ -773,9 +788,8 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
             AY[i] = __builtin_amdgcn_readlane(iv, 8 + i) - (int)(ra - br0) - 1 - kRegM;
         }
     }
-    R DX[8], DY[8], wgt;
-    int IX[8], IY[8];
-    tap_coords<R>(J, w, live ? r : br0, live ? c : bc0, DX, DY, IX, IY, wgt);
+    const PixGeom<R> G(J, w, live ? r : br0, live ? c : bc0);
+    R wgt = G.wgt;
     if (PRE == kPreI64) wgt *= (R)2;
     const unsigned char *gbase = static_cast<const unsigned char *>(J.g);
     const int slot_bytes = (int)(J.slot_elems * 8);
@@ -797,9 +811,9 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         toff[k] = (e / kRegS) * ww + e % kRegS;
     }
     double pre[kFdPrefetch][NCH][kRegLoads];
-    auto fetch = [&](int i) {
-        const int xi = (i & 1) + 2 * ((i >> 1) & 1) + 4 * ((i >> 3) & 1);
-        const int yi = ((i >> 1) & 1) + 2 * ((i >> 2) & 1) + 4 * ((i >> 3) & 1);
+    auto fetch = [&](int i) {   // region of the tap processed at step i
+        const int xi = step_q1(i) + 2 * step_q2(i) + 4 * step_q4(i);
+        const int yi = step_q2(i) + 2 * step_q3(i) + 4 * step_q4(i);
         const int sb = AY[yi] * ww + AX[xi];   // uniform
 #pragma unroll
         for (int k = 0; k < kRegLoads; ++k) {
@@ -823,20 +837,33 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
     for (int j = 0; j < kFdPrefetch; ++j) fetch(j);
     stage(0);
     lds_barrier();
+    R gdx[2], gdy[2];   // remainders of the current group's abscissae / ordinates
+    int glx[2], gly[2];  // their region offsets (gly in samples of whole rows)
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i + kFdPrefetch < 16) fetch(i + kFdPrefetch);
-        const int q1 = i & 1, q2 = (i >> 1) & 1, q3 = (i >> 2) & 1, q4 = (i >> 3) & 1;
-        const int xi = q1 + 2 * q2 + 4 * q4, yi = q2 + 2 * q3 + 4 * q4;
-        const ZpTap<R> z(DX[xi], DY[yi]);
-        // sample position relative to the region (clamped; lanes outside are redone below)
-        const int lx = IX[xi] - AX[xi], ly = IY[yi] - AY[yi];
-        outside |= !(lx >= 1 && lx <= kRegS - 2 && ly >= 1 && ly <= kRegS - 2);
-        const int base = min(max(ly, 1), kRegS - 2) * kRegS + min(max(lx, 1), kRegS - 2);
+        const int q1 = step_q1(i), q2 = step_q2(i), q3 = step_q3(i), q4 = step_q4(i);
+        if ((i & 3) == 0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int xi = u + 2 * q2 + 4 * q4, yi = q2 + 2 * u + 4 * q4;
+                const R x = G.x(xi), y = G.y(yi);
+                const R rx = rint(x), ry = rint(y);
+                gdx[u] = x - rx;
+                gdy[u] = y - ry;
+                // position in the region (clamped; a lane whose stencil leaves it is redone below)
+                const int lx = min(max((int)rx, 1), ww - 2) - AX[xi], ly = min(max((int)ry, 1), w.h - 2) - AY[yi];
+                outside |= (unsigned)(lx - 1) > (unsigned)(kRegS - 3) || (unsigned)(ly - 1) > (unsigned)(kRegS - 3);
+                glx[u] = min(max(lx, 1), kRegS - 2);
+                gly[u] = min(max(ly, 1), kRegS - 2) * kRegS;
+            }
+        }
+        const ZpTap<R> z(gdx[q1], gdy[q3]);
+        const int base = (gly[q3] + glx[q1]) * 8;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const double *L = lds[i & 1][ch];
-            const R F8 = z.apply([&](int e) { return L[e]; }, base, kRegS);
+            const unsigned char *L = reinterpret_cast<const unsigned char *>(lds[i & 1][ch]);
+            const R F8 = z.apply([&](int off) { return *reinterpret_cast<const double *>(L + off); }, base, 8, kRegS * 8);
             acc[ch] = ((q1 + q2 + q3 + q4) & 1) ? acc[ch] - F8 : acc[ch] + F8;   // w_i = (-1)^(q1+..+q4) w
             // keep this tap's arithmetic here: otherwise it is sunk into the final store
             // block and every tap's samples stay live in registers until then
