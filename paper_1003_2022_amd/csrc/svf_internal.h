@@ -8,8 +8,9 @@
 namespace svf {
 
 constexpr int kScanThreads = 256;    // one work-group per (tile, channel) window
-constexpr int kScanChunks = 4;       // window width <= 4 * 256 columns
-constexpr int kMaxWindow = kScanThreads * kScanChunks;
+constexpr int kScanCols = 2 * kScanThreads;   // columns per chunk: two adjacent columns per thread
+constexpr int kScanChunks = 2;       // window width <= 2 * 512 columns
+constexpr int kMaxWindow = kScanCols * kScanChunks;
 constexpr int kSmapRows = 4;         // scale map: each thread handles 4 rows of a 64 x 16 block
 constexpr int kSmapCols = 64;        // scale map: block of 64 columns x 16 rows
 constexpr int kMaxChannels = 4;

@@ -440,95 +440,136 @@ __device__ __forceinline__ typename A::T wave_scan(typename A::T v)
 }
 
 template <class A, int KC>
-struct ScanLds {
+struct alignas(16) ScanLds {
     // double-buffered by row parity
-    typename A::T p45[2][KC * kScanThreads + 2];   // previous row g45 at index c + 1 (index 0 stays zero)
-    typename A::T pb[2][KC * kScanThreads + 2];    // previous row g_b at index c (index >= w stays zero)
+    typename A::T p45[2][KC * kScanCols + 2];   // previous row g45 at index c + 1 (index 0 stays zero)
+    typename A::T pb[2][KC * kScanCols + 2];    // previous row g_b at index c (index >= w stays zero)
     typename A::T wsum[2][KC][kScanThreads / 64];
+    float row[2][KC * kScanCols];               // input rows published by the loader wave
 };
 
-constexpr int kPrefetchRows = 8;
+constexpr int kLoadDepth = 4;   // input rows the loader wave has in flight
 
-// One window: rows [w.r0, w.r0 + w.h) x cols [w.c0, w.c0 + w.w), channel ch of the
-// job's pass input, zero outside the image; result (g_b, or G for integers) into
-// gout[row * w.w + col].  Thread t owns columns c = k * 256 + t.  Input rows are
-// loaded kPrefetchRows ahead (unconditional loads at clamped addresses, masked
-// when consumed), and one LDS barrier per row orders the row exchange.
-template <class A, int IN, int KC>
-__device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, ScanLds<A, KC> &L)
+// The loader wave (threads kScanThreads .. kScanThreads + 63): loads the window's
+// input rows kLoadDepth ahead into registers (coalesced, clamped addresses) and
+// publishes row r + 1 into the LDS ring during row r, zero outside the image and
+// the window.  Its memory queue holds loads only, so its waits are exact, and the
+// compute waves never wait on memory.  Barriers match the compute waves' one per row.
+template <int IN, int KC>
+__device__ void load_rows(const Job &J, int ch, const Window w, float (*ring)[KC * kScanCols])
 {
-    using T = typename A::T;
     using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int K = (w.w + kScanThreads - 1) / kScanThreads;   // <= KC
-    for (int i = t; i < KC * kScanThreads + 2; i += kScanThreads) {
-        L.p45[0][i] = A::zero(); L.pb[0][i] = A::zero();
-        L.p45[1][i] = A::zero(); L.pb[1][i] = A::zero();
-    }
-    T p90[KC];
-    bool colin[KC];
-    int64_t colidx[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        p90[k] = A::zero();
-        const int c = k * kScanThreads + t;
-        const int64_t C = w.c0 + c;
-        colin[k] = k < K && c < w.w && C >= 0 && C < J.W;
-        colidx[k] = min(max(C, (int64_t)0), J.W - 1) * J.C + ch;
-    }
+    constexpr int NV = KC * kScanCols / 64;   // values per lane and row
+    const int lane = threadIdx.x & 63;
     const E *in = static_cast<const E *>(J.in);
-    E ring[kPrefetchRows][KC];
+    E regs[kLoadDepth][NV];
     auto issue = [&](int rr, E *dst) {
         const int64_t R = min(max(w.r0 + rr, (int64_t)0), J.H - 1);
         const E *rowp = in + R * J.in_rs;
 #pragma unroll
-        for (int k = 0; k < KC; ++k) dst[k] = rowp[colidx[k]];
+        for (int j = 0; j < NV; ++j) {
+            const int64_t C = min(max(w.c0 + lane + 64 * j, (int64_t)0), J.W - 1);
+            dst[j] = rowp[C * J.C + ch];
+        }
+    };
+    auto put = [&](int rr, const E *src) {
+        const int64_t R = w.r0 + rr;
+        const bool rin = R >= 0 && R < J.H;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int c = lane + 64 * j;
+            const int64_t C = w.c0 + c;
+            ring[rr & 1][c] = (rin && c < w.w && C >= 0 && C < J.W) ? (float)src[j] : 0.f;
+        }
     };
 #pragma unroll
-    for (int d = 0; d < kPrefetchRows; ++d) issue(d, ring[d]);
+    for (int d = 0; d < kLoadDepth; ++d) issue(d, regs[d]);
+    put(0, regs[0]);
     lds_barrier();
-    for (int rr0 = 0; rr0 < w.h; rr0 += kPrefetchRows) {
+    for (int rr0 = 0; rr0 < w.h; rr0 += kLoadDepth) {
 #pragma unroll
-        for (int d = 0; d < kPrefetchRows; ++d) {
+        for (int d = 0; d < kLoadDepth; ++d) {
             const int rr = rr0 + d;
             if (rr >= w.h) break;   // uniform
-            const int64_t R = w.r0 + rr;
-            const bool rin = R >= 0 && R < J.H;
-            T v[KC];
-#pragma unroll
-            for (int k = 0; k < KC; ++k) v[k] = A::from((rin && colin[k]) ? (double)ring[d][k] : 0.0);
-            issue(rr + kPrefetchRows, ring[d]);   // row rr + kPrefetchRows, clamped (value unused past the end)
-            const int pp = rr & 1;                // LDS buffer written by this row
-            // RS1: prefix along the row (wave scans, wave totals through LDS)
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k < K) {
-                    v[k] = wave_scan<A>(v[k]);
-                    if (lane == 63) L.wsum[pp][k][wave] = v[k];
-                }
-            }
+            issue(rr + kLoadDepth, regs[d]);           // row rr is in LDS already: reuse its registers
+            put(rr + 1, regs[(d + 1) % kLoadDepth]);   // row rr + 1, for the compute waves' next row
             lds_barrier();
-            T carry = A::zero();
+        }
+    }
+}
+
+// One window: rows [w.r0, w.r0 + w.h) x cols [w.c0, w.c0 + w.w), channel ch of the
+// job's pass input, zero outside the image; result (g_b, or G for integers) into
+// gout[row * w.w + col].  Compute thread t owns the adjacent columns c0 = k * 512 + 2t
+// and c1 = c0 + 1 of chunk k.  Per row: RS1 is the pair sum scanned over the wave
+// (DPP), the wave totals exchanged through LDS, and the pair split again with the
+// exclusive prefix (DPP wave shift); RS2..RS4 take one neighbour each from the
+// previous row: the column inside the pair from registers, the one across the pair
+// boundary from a double-buffered LDS row.  Input rows come from the loader wave
+// through LDS; one LDS barrier per row orders every exchange.
+template <class A, int IN, int KC>
+__device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, ScanLds<A, KC> &L)
+{
+    using T = typename A::T;
+    const int t = threadIdx.x;
+    if (t >= kScanThreads) {
+        load_rows<IN, KC>(J, ch, w, L.row);
+        return;
+    }
+    const int lane = t & 63, wave = t >> 6;
+    const int K = (w.w + kScanCols - 1) / kScanCols;   // <= KC
+    for (int i = t; i < KC * kScanCols + 2; i += kScanThreads) {
+        L.p45[0][i] = A::zero(); L.pb[0][i] = A::zero();
+        L.p45[1][i] = A::zero(); L.pb[1][i] = A::zero();
+    }
+    T p90[KC][2], prev45[KC], prevb[KC];   // g90 of both columns; last row's g45 at c0 and g_b at c1
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k < K) {
-                    T off = carry;
+    for (int k = 0; k < KC; ++k) p90[k][0] = p90[k][1] = prev45[k] = prevb[k] = A::zero();
+    lds_barrier();
+    for (int rr = 0; rr < w.h; ++rr) {
+        const int pp = rr & 1;   // LDS buffers written by this row
+        T v[KC][2], incl[KC];
+        // RS1: prefix of the pair sums over the wave, wave totals through LDS
 #pragma unroll
-                    for (int q = 0; q < kScanThreads / 64; ++q) {
-                        const T ws = L.wsum[pp][k][q];
-                        if (q < wave) off = A::add(off, ws);
-                        carry = A::add(carry, ws);
-                    }
-                    const int c = k * kScanThreads + t;
-                    const T g0 = A::add(v[k], off);
-                    const T g45 = A::s2add(g0, L.p45[pp ^ 1][c]);        // RS2: sqrt2 g0 + g45[r-1][c-1]
-                    p90[k] = A::add(g45, p90[k]);                        // RS3: g45 + g90[r-1][c]
-                    const T gb = A::s2add(p90[k], L.pb[pp ^ 1][c + 1]);  // RS4: sqrt2 g90 + gb[r-1][c+1]
-                    if (c < w.w) {
-                        L.p45[pp][c + 1] = g45;
-                        L.pb[pp][c] = gb;
-                        A::store(gout, (int64_t)rr * w.w + c, gb);
-                    }
+        for (int k = 0; k < KC; ++k) {
+            if (k < K) {
+                const float2 f = *reinterpret_cast<const float2 *>(&L.row[pp][k * kScanCols + 2 * t]);
+                v[k][0] = A::from((double)f.x);
+                v[k][1] = A::from((double)f.y);
+                incl[k] = wave_scan<A>(A::add(v[k][0], v[k][1]));
+                if (lane == 63) L.wsum[pp][k][wave] = incl[k];
+            }
+        }
+        lds_barrier();
+        T carry = A::zero();
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            if (k < K) {
+                T off = carry;
+#pragma unroll
+                for (int q = 0; q < kScanThreads / 64; ++q) {
+                    const T ws = L.wsum[pp][k][q];
+                    if (q < wave) off = A::add(off, ws);
+                    carry = A::add(carry, ws);
+                }
+                const int c0 = k * kScanCols + 2 * t;
+                // prefix before c0 = lane - 1's inclusive pair prefix (zero in lane 0) + off
+                const T excl = A::template dpp<0x138, 0xf>(incl[k]);   // wave_shr:1
+                const T g00 = A::add(A::add(off, excl), v[k][0]);
+                const T g01 = A::add(g00, v[k][1]);
+                const T g450 = A::s2add(g00, L.p45[pp ^ 1][c0]);       // RS2: sqrt2 g0 + g45[r-1][c-1]
+                const T g451 = A::s2add(g01, prev45[k]);
+                p90[k][0] = A::add(g450, p90[k][0]);                   // RS3: g45 + g90[r-1][c]
+                p90[k][1] = A::add(g451, p90[k][1]);
+                const T gb0 = A::s2add(p90[k][0], prevb[k]);           // RS4: sqrt2 g90 + gb[r-1][c+1]
+                const T gb1 = A::s2add(p90[k][1], L.pb[pp ^ 1][c0 + 2]);
+                prev45[k] = g450;
+                prevb[k] = (c0 + 1 < w.w) ? gb1 : A::zero();           // zero beyond the window
+                L.p45[pp][c0 + 2] = g451;
+                if (c0 < w.w) {
+                    L.pb[pp][c0] = gb0;
+                    A::store(gout, (int64_t)rr * w.w + c0, gb0);
+                    if (c0 + 1 < w.w) A::store(gout, (int64_t)rr * w.w + c0 + 1, gb1);
                 }
             }
         }
@@ -536,7 +577,7 @@ __device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, S
 }
 
 template <class A, int IN, int KC>
-__global__ __launch_bounds__(kScanThreads) void k_preint(Job J)
+__global__ __launch_bounds__(kScanThreads + 64) void k_preint(Job J)
 {
     __shared__ ScanLds<A, KC> L;
     const int lt = blockIdx.x / J.C, ch = blockIdx.x - lt * J.C;
@@ -547,7 +588,7 @@ __global__ __launch_bounds__(kScanThreads) void k_preint(Job J)
 }
 
 template <class A, int KC>
-__global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(kScanThreads + 64) void k_preint_batch(const Job *jobs, int n, int total)
 {
     __shared__ ScanLds<A, KC> L;
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -564,7 +605,7 @@ __global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, 
 }
 
 template <class A, int IN>
-__global__ __launch_bounds__(kScanThreads) void k_preint_window(Job J, int ch, Window w, void *g)
+__global__ __launch_bounds__(kScanThreads + 64) void k_preint_window(Job J, int ch, Window w, void *g)
 {
     __shared__ ScanLds<A, kScanChunks> L;
     sweep_window<A, IN, kScanChunks>(J, ch, w, g, L);
@@ -907,9 +948,9 @@ template <class A, int KC>
 hipError_t launch_preint_kc(const Job &j, int nb, hipStream_t s)
 {
     if (j.in_type == kInF32)
-        hipLaunchKernelGGL((k_preint<A, kInF32, KC>), dim3(nb), dim3(kScanThreads), 0, s, j);
+        hipLaunchKernelGGL((k_preint<A, kInF32, KC>), dim3(nb), dim3(kScanThreads + 64), 0, s, j);
     else
-        hipLaunchKernelGGL((k_preint<A, kInU16, KC>), dim3(nb), dim3(kScanThreads), 0, s, j);
+        hipLaunchKernelGGL((k_preint<A, kInU16, KC>), dim3(nb), dim3(kScanThreads + 64), 0, s, j);
     return hipGetLastError();
 }
 
@@ -918,12 +959,8 @@ hipError_t launch_preint_t(const Job &j, hipStream_t s)
 {
     const int nb = (j.tr1 - j.tr0) * j.ntc * j.C;
     if (nb <= 0) return hipSuccess;
-    switch (chunks_for(j.T, j.cap)) {
-    case 1: return launch_preint_kc<A, 1>(j, nb, s);
-    case 2: return launch_preint_kc<A, 2>(j, nb, s);
-    case 3: return launch_preint_kc<A, 3>(j, nb, s);
-    default: return launch_preint_kc<A, 4>(j, nb, s);
-    }
+    if (chunks_for(j.T, j.cap) == 1) return launch_preint_kc<A, 1>(j, nb, s);
+    return launch_preint_kc<A, kScanChunks>(j, nb, s);
 }
 
 }  // namespace
@@ -936,7 +973,7 @@ int64_t slot_elems_for(int T, int cap)
 
 int chunks_for(int T, int cap)
 {
-    return (T + 2 * cap + 5 + kScanThreads - 1) / kScanThreads;
+    return (T + 2 * cap + 5 + kScanCols - 1) / kScanCols;
 }
 
 int scale_map_blocks(int64_t H, int64_t W)
@@ -985,16 +1022,16 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
     win.r0 = r0; win.c0 = c0; win.h = h; win.w = w;
     switch (j.preint) {
     case kPreF64:
-        if (j.in_type == kInF32) hipLaunchKernelGGL((k_preint_window<ArF64, kInF32>), dim3(1), dim3(kScanThreads), 0, s, j, channel, win, g);
-        else hipLaunchKernelGGL((k_preint_window<ArF64, kInU16>), dim3(1), dim3(kScanThreads), 0, s, j, channel, win, g);
+        if (j.in_type == kInF32) hipLaunchKernelGGL((k_preint_window<ArF64, kInF32>), dim3(1), dim3(kScanThreads + 64), 0, s, j, channel, win, g);
+        else hipLaunchKernelGGL((k_preint_window<ArF64, kInU16>), dim3(1), dim3(kScanThreads + 64), 0, s, j, channel, win, g);
         break;
     case kPreF32C:
-        if (j.in_type == kInF32) hipLaunchKernelGGL((k_preint_window<ArF32C, kInF32>), dim3(1), dim3(kScanThreads), 0, s, j, channel, win, g);
-        else hipLaunchKernelGGL((k_preint_window<ArF32C, kInU16>), dim3(1), dim3(kScanThreads), 0, s, j, channel, win, g);
+        if (j.in_type == kInF32) hipLaunchKernelGGL((k_preint_window<ArF32C, kInF32>), dim3(1), dim3(kScanThreads + 64), 0, s, j, channel, win, g);
+        else hipLaunchKernelGGL((k_preint_window<ArF32C, kInU16>), dim3(1), dim3(kScanThreads + 64), 0, s, j, channel, win, g);
         break;
     case kPreI64:
         if (j.in_type != kInU16) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_preint_window<ArI64, kInU16>), dim3(1), dim3(kScanThreads), 0, s, j, channel, win, g);
+        hipLaunchKernelGGL((k_preint_window<ArI64, kInU16>), dim3(1), dim3(kScanThreads + 64), 0, s, j, channel, win, g);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -1047,14 +1084,10 @@ hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid
 {
     if (total_tiles == 0) return hipSuccess;
     grid = std::max(1, std::min(grid, total_tiles));
-#define SVF_PB(A, KC) hipLaunchKernelGGL((k_preint_batch<A, KC>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles)
+#define SVF_PB(A, KC) hipLaunchKernelGGL((k_preint_batch<A, KC>), dim3(grid), dim3(kScanThreads + 64), 0, s, jobs, n, total_tiles)
 #define SVF_PB_KC(A)              \
-    switch (kc) {                 \
-    case 1: SVF_PB(A, 1); break;  \
-    case 2: SVF_PB(A, 2); break;  \
-    case 3: SVF_PB(A, 3); break;  \
-    default: SVF_PB(A, 4); break; \
-    }
+    if (kc == 1) SVF_PB(A, 1);    \
+    else SVF_PB(A, kScanChunks);
     switch (preint) {
     case kPreF64: SVF_PB_KC(ArF64); break;
     case kPreF32C: SVF_PB_KC(ArF32C); break;
