@@ -174,10 +174,13 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
  * Many images in one launch sequence: n images, each with its own field and
  * order (1..3).  All tiles of all images share one scale-map launch and, per
  * pass, one pre-integration and one finite-difference launch over a device
- * descriptor table (persistent work lists).  With use_graph != 0 the launch
- * sequence is captured once per distinct shape set into a HIP graph and
- * replayed.  Results are identical to n svf_filter calls.  Returns after
- * enqueueing (the descriptor upload is stream-ordered).
+ * descriptor table (a work-group finds its image by a search over prefix
+ * counts).  With use_graph != 0 the launch sequence is captured once per
+ * distinct shape set into a HIP graph and replayed.  Results equal n
+ * svf_filter calls with the same options (opts.tile 0 means 256 here) up to
+ * rounding: the batched pre-integration (many small windows) keeps one column
+ * per thread and sums in another order than the single-image sweep.  Returns
+ * after enqueueing (the descriptor upload is stream-ordered).
  */
 svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
                             const svf_opts *opts, svf_image *out, hipStream_t stream, int use_graph);
@@ -190,9 +193,9 @@ svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_
  * pass (pre-integration + finite difference, preceded by the scale map for a
  * request's first pass) of the requests in flight, oldest first, up to a
  * per-step work budget, all through the batched persistent kernels.  Requests
- * join and leave between steps.  Each request computes exactly what svf_filter computes with the same
- * options (opts.tile 0 means 256 here), so its result does not depend on the
- * mix it ran in.  Input, field and output stay in caller-owned device memory
+ * join and leave between steps.  Each request computes what
+ * svf_filter_batch computes for it (svf_filter's result up to rounding;
+ * opts.tile 0 means 256 here), bit for bit whatever the mix it ran in.  Input, field and output stay in caller-owned device memory
  * that must remain valid until the request is done.  The integer
  * pre-integration is not offered by the server (opts.preint must be F64 or
  * F32C).

@@ -169,7 +169,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         p.off_tstat = off_fill[i];
         p.off_scales = off_scales[i];
         p.off_g = off_g[i];
-        kc = std::max(kc, chunks_for(p.T, p.cap));
+        kc = std::max(kc, batch_chunks_for(p.T, p.cap));
         svf_opts oi = o;
         Job base = base_job(&in[i], &fields[i], orders[i], &oi, p, ws);
         base.out = static_cast<float *>(out[i].data);

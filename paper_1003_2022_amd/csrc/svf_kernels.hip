@@ -456,7 +456,7 @@ constexpr int kLoadDepth = 4;   // input rows the loader wave has in flight
 // the window.  Its memory queue holds loads only, so its waits are exact, and the
 // compute waves never wait on memory.  Barriers match the compute waves' one per row.
 template <int IN, int KC>
-__device__ void load_rows(const Job &J, int ch, const Window w, float (*ring)[KC * kScanCols])
+__device__ __forceinline__ void load_rows(const Job &J, int ch, const Window w, float (*ring)[KC * kScanCols])
 {
     using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
     constexpr int NV = KC * kScanCols / 64;   // values per lane and row
@@ -508,7 +508,7 @@ __device__ void load_rows(const Job &J, int ch, const Window w, float (*ring)[KC
 // boundary from a double-buffered LDS row.  Input rows come from the loader wave
 // through LDS; one LDS barrier per row orders every exchange.
 template <class A, int IN, int KC>
-__device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, ScanLds<A, KC> &L)
+__device__ __forceinline__ void sweep_window(const Job &J, int ch, const Window w, void *gout, ScanLds<A, KC> &L)
 {
     using T = typename A::T;
     const int t = threadIdx.x;
@@ -576,6 +576,104 @@ __device__ void sweep_window(const Job &J, int ch, const Window w, void *gout, S
     }
 }
 
+// Row sweep for the batched launches (many small windows): one column per
+// thread in chunks of 256 columns, input rows loaded kBatchPrefetch ahead by the
+// compute threads themselves (unconditional loads at clamped addresses, masked
+// when consumed), wave totals and the previous row through LDS, one barrier per
+// row.  Same recursions as sweep_window, summed in the order of one column per
+// thread, so its g equals sweep_window's up to rounding.  With four waves and no
+// loader wave a work-group is small, so more windows run at once.
+constexpr int kBatchCols = kScanThreads;   // columns per chunk
+constexpr int kBatchChunks = kMaxWindow / kBatchCols;
+constexpr int kBatchPrefetch = 8;
+
+template <class A, int KC>
+struct alignas(16) ScanLds1 {
+    typename A::T p45[2][KC * kBatchCols + 2];   // previous row g45 at index c + 1 (index 0 stays zero)
+    typename A::T pb[2][KC * kBatchCols + 2];    // previous row g_b at index c (index >= w stays zero)
+    typename A::T wsum[2][KC][kScanThreads / 64];
+};
+
+template <class A, int IN, int KC>
+__device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Window w, void *gout, ScanLds1<A, KC> &L)
+{
+    using T = typename A::T;
+    using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int K = (w.w + kBatchCols - 1) / kBatchCols;   // <= KC
+    for (int i = t; i < KC * kBatchCols + 2; i += kScanThreads) {
+        L.p45[0][i] = A::zero(); L.pb[0][i] = A::zero();
+        L.p45[1][i] = A::zero(); L.pb[1][i] = A::zero();
+    }
+    T p90[KC];
+    bool colin[KC];
+    int64_t colidx[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        p90[k] = A::zero();
+        const int c = k * kBatchCols + t;
+        const int64_t C = w.c0 + c;
+        colin[k] = k < K && c < w.w && C >= 0 && C < J.W;
+        colidx[k] = min(max(C, (int64_t)0), J.W - 1) * J.C + ch;
+    }
+    const E *in = static_cast<const E *>(J.in);
+    E ring[kBatchPrefetch][KC];
+    auto issue = [&](int rr, E *dst) {
+        const int64_t R = min(max(w.r0 + rr, (int64_t)0), J.H - 1);
+        const E *rowp = in + R * J.in_rs;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) dst[k] = rowp[colidx[k]];
+    };
+#pragma unroll
+    for (int d = 0; d < kBatchPrefetch; ++d) issue(d, ring[d]);
+    lds_barrier();
+    for (int rr0 = 0; rr0 < w.h; rr0 += kBatchPrefetch) {
+#pragma unroll
+        for (int d = 0; d < kBatchPrefetch; ++d) {
+            const int rr = rr0 + d;
+            if (rr >= w.h) break;   // uniform
+            const int64_t R = w.r0 + rr;
+            const bool rin = R >= 0 && R < J.H;
+            T v[KC];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) v[k] = A::from((rin && colin[k]) ? (double)ring[d][k] : 0.0);
+            issue(rr + kBatchPrefetch, ring[d]);   // row rr + kBatchPrefetch, clamped (value unused past the end)
+            const int pp = rr & 1;                 // LDS buffer written by this row
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (k < K) {
+                    v[k] = wave_scan<A>(v[k]);
+                    if (lane == 63) L.wsum[pp][k][wave] = v[k];
+                }
+            }
+            lds_barrier();
+            T carry = A::zero();
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (k < K) {
+                    T off = carry;
+#pragma unroll
+                    for (int q = 0; q < kScanThreads / 64; ++q) {
+                        const T ws = L.wsum[pp][k][q];
+                        if (q < wave) off = A::add(off, ws);
+                        carry = A::add(carry, ws);
+                    }
+                    const int c = k * kBatchCols + t;
+                    const T g0 = A::add(v[k], off);
+                    const T g45 = A::s2add(g0, L.p45[pp ^ 1][c]);        // RS2: sqrt2 g0 + g45[r-1][c-1]
+                    p90[k] = A::add(g45, p90[k]);                        // RS3: g45 + g90[r-1][c]
+                    const T gb = A::s2add(p90[k], L.pb[pp ^ 1][c + 1]);  // RS4: sqrt2 g90 + gb[r-1][c+1]
+                    if (c < w.w) {
+                        L.p45[pp][c + 1] = g45;
+                        L.pb[pp][c] = gb;
+                        A::store(gout, (int64_t)rr * w.w + c, gb);
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <class A, int IN, int KC>
 __global__ __launch_bounds__(kScanThreads + 64) void k_preint(Job J)
 {
@@ -588,9 +686,9 @@ __global__ __launch_bounds__(kScanThreads + 64) void k_preint(Job J)
 }
 
 template <class A, int KC>
-__global__ __launch_bounds__(kScanThreads + 64) void k_preint_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, int n, int total)
 {
-    __shared__ ScanLds<A, KC> L;
+    __shared__ ScanLds1<A, KC> L;
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 0));
         const Job &J = jobs[j];
@@ -598,9 +696,9 @@ __global__ __launch_bounds__(kScanThreads + 64) void k_preint_batch(const Job *j
         const int tile = lt / J.C, ch = lt - tile * J.C;
         const Window w = window_of(J, tile);
         void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
-        if (J.in_type == kInU16) sweep_window<A, kInU16, KC>(J, ch, w, gout, L);
-        else sweep_window<A, kInF32, KC>(J, ch, w, gout, L);
-        lds_barrier();
+        if (J.in_type == kInU16) sweep_window_cols<A, kInU16, KC>(J, ch, w, gout, L);
+        else sweep_window_cols<A, kInF32, KC>(J, ch, w, gout, L);
+        lds_barrier();   // the shared records are reused by the next window
     }
 }
 
@@ -976,6 +1074,11 @@ int chunks_for(int T, int cap)
     return (T + 2 * cap + 5 + kScanCols - 1) / kScanCols;
 }
 
+int batch_chunks_for(int T, int cap)
+{
+    return (T + 2 * cap + 5 + kBatchCols - 1) / kBatchCols;
+}
+
 int scale_map_blocks(int64_t H, int64_t W)
 {
     return (int)(((W + kSmapCols - 1) / kSmapCols) * ((H + 4 * kSmapRows - 1) / (4 * kSmapRows)));
@@ -1084,10 +1187,14 @@ hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid
 {
     if (total_tiles == 0) return hipSuccess;
     grid = std::max(1, std::min(grid, total_tiles));
-#define SVF_PB(A, KC) hipLaunchKernelGGL((k_preint_batch<A, KC>), dim3(grid), dim3(kScanThreads + 64), 0, s, jobs, n, total_tiles)
+#define SVF_PB(A, KC) hipLaunchKernelGGL((k_preint_batch<A, KC>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles)
 #define SVF_PB_KC(A)              \
-    if (kc == 1) SVF_PB(A, 1);    \
-    else SVF_PB(A, kScanChunks);
+    switch (kc) {                 \
+    case 1: SVF_PB(A, 1); break;  \
+    case 2: SVF_PB(A, 2); break;  \
+    case 3: SVF_PB(A, 3); break;  \
+    default: SVF_PB(A, 4); break; \
+    }
     switch (preint) {
     case kPreF64: SVF_PB_KC(ArF64); break;
     case kPreF32C: SVF_PB_KC(ArF32C); break;

@@ -239,7 +239,7 @@ void loop(Server *S)
             pp.off_tstat = q.off + p.off_tstat;
             pp.off_scales = q.off + p.off_scales;
             pp.off_g = q.off + p.off_g;
-            kc = std::max(kc, chunks_for(p.T, p.cap));
+            kc = std::max(kc, batch_chunks_for(p.T, p.cap));
             Job base = base_job(&q.r.in, &q.r.field, q.r.order, &S->cfg.opts, pp, S->arena_base);
             base.out = static_cast<float *>(q.r.out.data);
             base.out_rs = q.r.out.row_stride;

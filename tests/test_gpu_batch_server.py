@@ -1,9 +1,11 @@
 """GPU tests of the batched launch path and of the serving loop.
 
 * svf_filter_batch (eager and HIP-graph replays) equals per-image svf_filter
-  with the same options, and the oracle;
+  with the same options to 1e-6 (the batched pre-integration sums in another
+  order; the outputs are float32), every replay equals the first bit for bit,
+  and the oracle to 1e-5;
 * the server: every request's output is bitwise identical whether it is served
-  alone or in a mix, equals svf_filter with the same options to 1e-12, and
+  alone or in a mix, equals svf_filter with the same options to 1e-6, and
   equals the CPU FP64 oracle to 1e-5 (relative, per pixel);
 * admission: a request larger than the memory budget is rejected at submit.
 """
@@ -83,6 +85,7 @@ def test_batch_matches_single_and_oracle(ctx, cases, use_graph):
     stream = torch.cuda.Stream()
     o = P.default_opts(tile=256)
     reps = 3 if use_graph else 1
+    first = []
     for rep in range(reps):
         for t in outs:
             t.zero_()
@@ -97,7 +100,11 @@ def test_batch_matches_single_and_oracle(ctx, cases, use_graph):
             got = outs[i].cpu().numpy()
             e = rel_err(got, ref)
             print(f"graph={use_graph} rep {rep} case {i}: vs single {e:.2e}", flush=True)
-            assert e <= 1e-12
+            assert e <= 1e-6
+            if rep == 0:
+                first.append(got)
+            else:
+                assert np.array_equal(got, first[i]), f"replay {rep} differs from the first"
     for i in (0, 2):
         img, fld, order = cases[i][:3]
         ref = oracle.filter(img, fld, oracle.FIELD_SRT3, order)
@@ -160,7 +167,7 @@ def test_server_mix_equals_alone(ctx, cases):
         assert res[i].t_done_us >= res[i].t_admit_us >= res[i].t_submit_us
     for i, c in enumerate(cases):
         ref = single(ctx, c[3], c[4], c[2], tile=256)
-        assert rel_err(alone[i], ref) <= 1e-12
+        assert rel_err(alone[i], ref) <= 1e-6
     img, fld, order = cases[2][:3]
     assert rel_err(alone[2], oracle.filter(img, fld, oracle.FIELD_SRT3, order)) <= 1e-5
 
