@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, by ``__graft_entry__.smoke()``
 and by the CPU-baseline leg of ``bench.py``.  The product package never imports
 it.  The arithmetic lives in ``svf_oracle.c`` (plain C, binary64); this module
-only marshals numpy arrays and composes passes.
+only marshals numpy arrays, composes passes and gathers boundary extensions.
 
 What it computes (Chaudhury, Munoz-Barrutia, Unser, "Fast space-variant
 elliptical filtering using box splines"):
@@ -19,6 +19,10 @@ elliptical filtering using box splines"):
   ZP interpolation) or with the direct sum  sum_k f[k] beta^4_{a(n)}(n - k).
 * ``filter_region(...)`` -- the same on a sub-rectangle of a large image (for
   sampled parity checks), pulling in only the region every pass depends on.
+* ``boundary`` (both) -- what each pass reads outside the image: zero, the
+  nearest pixel, or the half-sample mirror; the recursion of Sec. 2.1 needs some
+  such condition and the paper does not fix one.  Each pass then is the direct
+  sum over the image extended by ``boundary_index``.
 """
 from __future__ import annotations
 
@@ -242,25 +246,70 @@ def _pass(img, fr0, fc0, a_rect, r0, c0, method, tile):
     return out
 
 
-def filter_scales(img: np.ndarray, a_pass: np.ndarray, order: int = 1, method: str = "fast", tile: int = 32):
+# Values of the image outside its border (the paper leaves the boundary conditions
+# of the running sums open, Sec. 2.1): zero, replicate the nearest pixel, or the
+# half-sample symmetric mirror (f[-1] = f[0], f[-2] = f[1], ...; period 2N).
+BOUNDARY_ZERO, BOUNDARY_REPLICATE, BOUNDARY_SYMMETRIC = 0, 1, 2
+
+
+def boundary_index(i, N: int, boundary: int):
+    """Image index whose value the (possibly outside) index i takes under the rule."""
+    i = np.asarray(i, dtype=np.int64)
+    if boundary == BOUNDARY_REPLICATE:
+        return np.clip(i, 0, N - 1)
+    if boundary == BOUNDARY_SYMMETRIC:
+        m = np.mod(i, 2 * N)
+        return np.where(m >= N, 2 * N - 1 - m, m)
+    raise ValueError(boundary)
+
+
+def _margins(a):
+    """Rows / columns beyond an output rectangle that its pixels may read (support + ZP reach)."""
+    rx, ry = support_halfwidths(a)
+    return int(np.ceil(float(ry.max()))) + 3, int(np.ceil(float(rx.max()))) + 3
+
+
+def _pass_rule(src, sr0, sc0, H, W, a_rect, r0, c0, method, tile, boundary):
+    """One pass on the output rectangle (r0, c0) + a_rect.shape[:2] of an H x W image.
+
+    src holds the pass input on image rows sr0.. and columns sc0.. .  Zero rule:
+    nothing outside the image.  Other rules: the input on the rectangle grown by
+    every read's reach is gathered through boundary_index (so an output reads the
+    direct sum over the extended lattice), and the pass runs on that extension.
+    """
+    if boundary == BOUNDARY_ZERO:
+        return _pass(src, sr0, sc0, a_rect, r0, c0, method, tile)
+    h, w = a_rect.shape[:2]
+    gy, gx = _margins(a_rect)
+    ri = boundary_index(np.arange(r0 - gy, r0 + h + gy), H, boundary) - sr0
+    ci = boundary_index(np.arange(c0 - gx, c0 + w + gx), W, boundary) - sc0
+    if ri.min() < 0 or ri.max() >= src.shape[0] or ci.min() < 0 or ci.max() >= src.shape[1]:
+        raise RuntimeError("pass input does not cover the reflected reads")
+    return _pass(np.asarray(src)[np.ix_(ri, ci)], r0 - gy, c0 - gx, a_rect, r0, c0, method, tile)
+
+
+def filter_scales(img: np.ndarray, a_pass: np.ndarray, order: int = 1, method: str = "fast", tile: int = 32,
+                  boundary: int = BOUNDARY_ZERO):
     """Order-m filter of a whole single-channel image given per-pass scales (H, W, 4).
 
-    Pass p reads the (binary64) output of pass p-1, zero outside the image (Sec. 3.3).
+    Pass p reads the (binary64) output of pass p-1, extended beyond the image by the
+    boundary rule (zero by default) (Sec. 3.3).
     """
     H, W = img.shape
     cur = img
     for _ in range(order):
-        cur = _pass(cur, 0, 0, a_pass, 0, 0, method, tile)
+        cur = _pass_rule(cur, 0, 0, H, W, a_pass, 0, 0, method, tile, boundary)
     return cur
 
 
 def filter(img: np.ndarray, field: np.ndarray, kind: int, order: int = 1, eps: float = DEFAULT_EPS,
-           method: str = "fast", tile: int = 32):
+           method: str = "fast", tile: int = 32, boundary: int = BOUNDARY_ZERO):
     """Order-m filter of an image (H, W) or (H, W, C) with a field (H, W, 3|4); returns float64."""
     a, _ = scales(field, kind, order, eps)
     if img.ndim == 3:
-        return np.stack([filter_scales(img[..., ch], a, order, method, tile) for ch in range(img.shape[2])], -1)
-    return filter_scales(img, a, order, method, tile)
+        return np.stack([filter_scales(img[..., ch], a, order, method, tile, boundary) for ch in range(img.shape[2])],
+                        -1)
+    return filter_scales(img, a, order, method, tile, boundary)
 
 
 def _grow(rect, gy, gx, H, W):
@@ -271,17 +320,16 @@ def _grow(rect, gy, gx, H, W):
 
 
 def filter_region(img: np.ndarray, field: np.ndarray, kind: int, order: int, rect, eps: float = DEFAULT_EPS,
-                  method: str = "fast", tile: int = 32) -> np.ndarray:
+                  method: str = "fast", tile: int = 32, boundary: int = BOUNDARY_ZERO) -> np.ndarray:
     """Order-m output on rect = (r0, c0, h, w) of a large single-channel image.
 
-    Pass m needs pass m-1 on rect grown by pass m's support; the chain of
-    regions is built backwards from the per-pass scales, computed only where
-    needed.  Values outside the image are zero; values inside the image but
-    outside a region are never read by the outputs of the next region.
+    Pass m needs pass m-1 on rect grown by pass m's reach, clipped to the image;
+    the chain of regions is built backwards from the per-pass scales, computed
+    only where needed.  Values outside the image follow the boundary rule; a
+    grown region that crosses a border reaches it, so the reflected or
+    replicated reads stay inside the region below.
     """
     H, W = img.shape
-    # bound on the support half-width over the whole chain, from a first solve on a generous region
-    probe = _grow(rect, 0, 0, H, W)
     regions = [tuple(rect)]
     a_cache = {}
 
@@ -294,15 +342,12 @@ def filter_region(img: np.ndarray, field: np.ndarray, kind: int, order: int, rec
 
     for _ in range(order - 1):
         cur = regions[-1]
-        a = a_for(cur)
-        rx, ry = support_halfwidths(a)
-        gx, gy = int(np.ceil(rx.max())) + 2, int(np.ceil(ry.max())) + 2
+        gy, gx = _margins(a_for(cur))
         regions.append(_grow(cur, gy, gx, H, W))
     regions = regions[::-1]   # regions[0] is pass 1's output region
-    del probe
     cur_img, fr0, fc0 = img, 0, 0
-    for p, rr in enumerate(regions):
+    for rr in regions:
         r0, c0, h, w = rr
-        out = _pass(cur_img, fr0, fc0, a_for(rr), r0, c0, method, tile)
+        out = _pass_rule(cur_img, fr0, fc0, H, W, a_for(rr), r0, c0, method, tile, boundary)
         cur_img, fr0, fc0 = out, r0, c0
     return cur_img

@@ -232,3 +232,69 @@ def test_fourier_correlation_with_gaussian(orc, paper):
     assert worst[1] >= paper["gaussian_correlation_min"]["m1"]
     assert worst[2] >= paper["gaussian_correlation_min"]["m2"]
     assert worst[2] > worst[1]
+
+
+# ----------------------------------------------------------------------------- boundary rules
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5])
+def test_boundary_index_matches_numpy_pad(orc, N):
+    # numpy.pad's 'edge' and 'symmetric' modes define replicate and the half-sample mirror
+    P = 3 * N + 4
+    base = np.arange(N)
+    idx = np.arange(-P, N + P)
+    np.testing.assert_array_equal(orc.boundary_index(idx, N, orc.BOUNDARY_REPLICATE), np.pad(base, P, mode="edge"))
+    np.testing.assert_array_equal(orc.boundary_index(idx, N, orc.BOUNDARY_SYMMETRIC),
+                                  np.pad(base, P, mode="symmetric"))
+
+
+@pytest.mark.parametrize("boundary,mode", [(1, "edge"), (2, "symmetric")])
+@pytest.mark.parametrize("shape,order", [((17, 13), 1), ((9, 22), 2), ((3, 4), 3)])
+def test_boundary_equals_direct_sum_on_padded_image(orc, boundary, mode, shape, order):
+    # direct sum over the lattice of the image extended by numpy.pad, one pass at a time
+    H, W = shape
+    f = I.uniform_image(H, W, 40 + H)
+    fld = I.srt_field(H, W, 40 + H, (1.0, 5.0), (1.0, 4.0), corr_len=5.0)
+    a, _ = orc.scales(fld, orc.FIELD_SRT3, order)
+    rx, ry = orc.support_halfwidths(a)
+    M = int(np.ceil(max(rx.max(), ry.max()))) + 6
+    ref = f.astype(np.float64)
+    for _ in range(order):
+        ref = orc._pass(np.pad(ref, M, mode=mode), -M, -M, a, 0, 0, "brute", 0)
+    got = orc.filter(f, fld, orc.FIELD_SRT3, order, method="fast", tile=5, boundary=boundary)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_boundary_keeps_constants_integer_a1_a3(orc, boundary):
+    # unit mass (a1, a3 integers) and a constant extension: the output is the constant up to the border
+    H, W = 21, 18
+    f = np.full((H, W), 3.5)
+    for a in ([2.0, 1.3, 1.0, 2.2], [3.0, 0.8, 2.0, 4.9]):
+        av = np.broadcast_to(a, (H, W, 4)).astype(np.float64)
+        np.testing.assert_allclose(orc.filter_scales(f, av, 2, "fast", 7, boundary), 3.5, rtol=1e-12)
+    zero = orc.filter_scales(f, av, 1, "fast", 7)
+    assert zero[0, 0] < 3.0   # the zero rule loses mass at the corner
+
+
+def test_symmetric_boundary_mirrors_with_the_image(orc):
+    # a field and image mirrored left-right give the mirrored output when the box
+    # directions are exchanged with their mirror images (u2 <-> u4)
+    H, W = 15, 12
+    f = I.uniform_image(H, W, 51).astype(np.float64)
+    a = I.scales_field(H, W, 51, 0.6, 4.0).astype(np.float64)
+    am = a[:, ::-1][..., [0, 3, 2, 1]]
+    out = orc.filter_scales(f, a, 1, "fast", 6, orc.BOUNDARY_SYMMETRIC)
+    outm = orc.filter_scales(f[:, ::-1], am, 1, "fast", 6, orc.BOUNDARY_SYMMETRIC)
+    np.testing.assert_allclose(outm[:, ::-1], out, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_boundary_region_matches_full(orc, boundary):
+    H, W = 36, 40
+    f = I.uniform_image(H, W, 15)
+    fld = I.srt_field(H, W, 15, (1.0, 4.0), (1.0, 4.0), corr_len=8.0)
+    full = orc.filter(f, fld, orc.FIELD_SRT3, 3, method="fast", tile=11, boundary=boundary)
+    for rect in [(0, 0, 7, 9), (30, 33, 6, 7), (10, 0, 5, 40)]:
+        r0, c0, h, w = rect
+        part = orc.filter_region(f, fld, orc.FIELD_SRT3, 3, rect, boundary=boundary)
+        np.testing.assert_allclose(part, full[r0:r0 + h, c0:c0 + w], rtol=1e-10, atol=1e-12)
