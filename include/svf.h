@@ -90,6 +90,17 @@ typedef struct {
     int64_t row_stride;  /* floats between rows, >= W * K; for SCALES4 a multiple of 4 (16-byte rows) */
 } svf_field;
 
+/* Values of a pass input outside the image.  The running sums (Sec. 2.1) need a
+ * boundary condition and the paper leaves it open.  Every pass of an order-m
+ * filter extends its own input by the rule: output n is
+ * sum_k f_ext[k] beta(n - k) over the whole lattice. */
+typedef enum {
+    SVF_BOUNDARY_ZERO = 0,       /* f = 0 outside the image (mass leaks at the borders) */
+    SVF_BOUNDARY_REPLICATE = 1,  /* f[i] = f[clamp(i, 0, N - 1)] per axis */
+    SVF_BOUNDARY_SYMMETRIC = 2   /* half-sample mirror per axis: f[-1 - i] = f[i], f[2N - 1 - i] = f[i]
+                                    (period 2N; an image narrower than the support reflects again) */
+} svf_boundary;
+
 typedef struct {
     int32_t preint;       /* svf_preint, default SVF_PRE_F64 */
     int32_t fd_fp32;      /* 0: finite difference and interpolation in binary64 (default);
@@ -105,7 +116,8 @@ typedef struct {
                              tile rows each) on internal streams, pass p of a band starting once
                              pass p-1 of the bands its windows reach is done.  Results are the
                              same bit for bit. */
-    int32_t reserved;
+    int32_t boundary;     /* svf_boundary: what every pass reads outside the image (default
+                             SVF_BOUNDARY_ZERO) */
 } svf_opts;
 
 typedef struct {

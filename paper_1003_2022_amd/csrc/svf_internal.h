@@ -18,6 +18,7 @@ constexpr int kMaxChannels = 4;
 enum Preint : int32_t { kPreF64 = 0, kPreF32C = 1, kPreI64 = 2 };
 enum InType : int32_t { kInF32 = 0, kInU16 = 1 };
 enum FieldKind : int32_t { kCov3 = 0, kSrt3 = 1, kScales4 = 2 };
+enum Boundary : int32_t { kBoundZero = 0, kBoundReplicate = 1, kBoundSymmetric = 2 };
 
 // Per-tile results of the scale map: largest support half-widths of the whole
 // filter (sizing the tile's pre-integration window) and pixel counts for the report.
@@ -60,7 +61,8 @@ struct Job {
     double inv_sqrt_m_d;
     double eps_full;         // floor on a^2 of the whole filter (order * eps per pass)
     // batched launches: first global tile / FD block / scale block of this job
-    int32_t tile_base, blk_base, smap_base, pad0;
+    int32_t tile_base, blk_base, smap_base;
+    int32_t boundary;        // Boundary: what a pass reads outside the image
     // single-image launches cover the tile rows [tr0, tr1) (scale map: their pixel rows)
     int32_t tr0, tr1;
 };

@@ -63,6 +63,26 @@ __device__ __forceinline__ Window window_of(const Job &J, int tile)
     return w;
 }
 
+// Image index whose value lattice index i (possibly outside [0, N)) takes in a
+// pass input.  Zero rule: any in-range index (the value is masked to zero by the
+// caller).  Replicate: the nearest index.  Symmetric: the half-sample mirror
+// f[-1 - i] = f[i], f[2N - 1 - i] = f[i] (period 2N; small images reflect
+// several times).
+__device__ __forceinline__ int64_t ext_index(int64_t i, int64_t N, int b)
+{
+    if (b == kBoundSymmetric) {
+        if (i < 0) i = -1 - i;
+        if (i >= N) {   // rare: only windows that cross the far border
+            const int n2 = 2 * (int)N;
+            int m = (int)i % n2;   // i < N + 2 * kMaxWindow: fits in 32 bits
+            if (m >= (int)N) m = n2 - 1 - m;
+            i = m;
+        }
+        return i;
+    }
+    return min(max(i, (int64_t)0), N - 1);
+}
+
 // XCD-aware block order: consecutive hardware work-group ids go round-robin over
 // the 8 XCDs; remap so that each XCD receives one contiguous range of logical
 // blocks (the blocks of a tile share its window in that XCD's L2).
@@ -309,14 +329,15 @@ __device__ void scale_map_block(const Job &J, int lb)
     __syncthreads();   // the shared records are reused by the next block of a persistent loop
 }
 
-__global__ __launch_bounds__(256) void k_scale_map(Job J)
+// occupancy 4 (<= 128 VGPRs, a few spilled): measured faster than 3 without spills or 5
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map(Job J)
 {
     // blocks of 16 pixel rows; the launch starts at the first row of tile row tr0
     const int nbx = (int)((J.W + kSmapCols - 1) / kSmapCols);
     scale_map_block(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
 }
 
-__global__ __launch_bounds__(256) void k_scale_map_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map_batch(const Job *jobs, int n, int total)
 {
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
@@ -451,9 +472,9 @@ struct alignas(16) ScanLds {
 constexpr int kLoadDepth = 4;   // input rows the loader wave has in flight
 
 // The loader wave (threads kScanThreads .. kScanThreads + 63): loads the window's
-// input rows kLoadDepth ahead into registers (coalesced, clamped addresses) and
-// publishes row r + 1 into the LDS ring during row r, zero outside the image and
-// the window.  Its memory queue holds loads only, so its waits are exact, and the
+// input rows kLoadDepth ahead into registers (coalesced; addresses mapped into
+// the image by the boundary rule) and publishes row r + 1 into the LDS ring during
+// row r, zero outside the window (and outside the image under the zero rule).  Its memory queue holds loads only, so its waits are exact, and the
 // compute waves never wait on memory.  Barriers match the compute waves' one per row.
 template <int IN, int KC>
 __device__ __forceinline__ void load_rows(const Job &J, int ch, const Window w, float (*ring)[KC * kScanCols])
@@ -463,24 +484,29 @@ __device__ __forceinline__ void load_rows(const Job &J, int ch, const Window w, 
     const int lane = threadIdx.x & 63;
     const E *in = static_cast<const E *>(J.in);
     E regs[kLoadDepth][NV];
+    const int bnd = J.boundary;
+    // per lane, once per window: element offset of each of its columns in a row,
+    // and which of them hold data (inside the window; inside the image, zero rule)
+    int32_t coff[NV];
+    uint32_t cmask = 0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int c = lane + 64 * j;
+        const int64_t C = w.c0 + c;
+        coff[j] = (int32_t)(ext_index(C, J.W, bnd) * J.C + ch);
+        if (c < w.w && (bnd != kBoundZero || (C >= 0 && C < J.W))) cmask |= 1u << j;
+    }
     auto issue = [&](int rr, E *dst) {
-        const int64_t R = min(max(w.r0 + rr, (int64_t)0), J.H - 1);
+        const int64_t R = ext_index(w.r0 + rr, J.H, bnd);
         const E *rowp = in + R * J.in_rs;
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const int64_t C = min(max(w.c0 + lane + 64 * j, (int64_t)0), J.W - 1);
-            dst[j] = rowp[C * J.C + ch];
-        }
+        for (int j = 0; j < NV; ++j) dst[j] = rowp[coff[j]];
     };
     auto put = [&](int rr, const E *src) {
         const int64_t R = w.r0 + rr;
-        const bool rin = R >= 0 && R < J.H;
+        const bool rin = bnd != kBoundZero || (R >= 0 && R < J.H);
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const int c = lane + 64 * j;
-            const int64_t C = w.c0 + c;
-            ring[rr & 1][c] = (rin && c < w.w && C >= 0 && C < J.W) ? (float)src[j] : 0.f;
-        }
+        for (int j = 0; j < NV; ++j) ring[rr & 1][lane + 64 * j] = (rin && ((cmask >> j) & 1u)) ? (float)src[j] : 0.f;
     };
 #pragma unroll
     for (int d = 0; d < kLoadDepth; ++d) issue(d, regs[d]);
@@ -499,7 +525,7 @@ __device__ __forceinline__ void load_rows(const Job &J, int ch, const Window w, 
 }
 
 // One window: rows [w.r0, w.r0 + w.h) x cols [w.c0, w.c0 + w.w), channel ch of the
-// job's pass input, zero outside the image; result (g_b, or G for integers) into
+// job's pass input, extended beyond the image by the job's boundary rule; result (g_b, or G for integers) into
 // gout[row * w.w + col].  Compute thread t owns the adjacent columns c0 = k * 512 + 2t
 // and c1 = c0 + 1 of chunk k.  Per row: RS1 is the pair sum scanned over the wave
 // (DPP), the wave totals exchanged through LDS, and the pair split again with the
@@ -605,6 +631,7 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
         L.p45[0][i] = A::zero(); L.pb[0][i] = A::zero();
         L.p45[1][i] = A::zero(); L.pb[1][i] = A::zero();
     }
+    const int bnd = J.boundary;
     T p90[KC];
     bool colin[KC];
     int64_t colidx[KC];
@@ -613,13 +640,13 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
         p90[k] = A::zero();
         const int c = k * kBatchCols + t;
         const int64_t C = w.c0 + c;
-        colin[k] = k < K && c < w.w && C >= 0 && C < J.W;
-        colidx[k] = min(max(C, (int64_t)0), J.W - 1) * J.C + ch;
+        colin[k] = k < K && c < w.w && (bnd != kBoundZero || (C >= 0 && C < J.W));
+        colidx[k] = ext_index(C, J.W, bnd) * J.C + ch;
     }
     const E *in = static_cast<const E *>(J.in);
     E ring[kBatchPrefetch][KC];
     auto issue = [&](int rr, E *dst) {
-        const int64_t R = min(max(w.r0 + rr, (int64_t)0), J.H - 1);
+        const int64_t R = ext_index(w.r0 + rr, J.H, bnd);
         const E *rowp = in + R * J.in_rs;
 #pragma unroll
         for (int k = 0; k < KC; ++k) dst[k] = rowp[colidx[k]];
@@ -633,7 +660,7 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
             const int rr = rr0 + d;
             if (rr >= w.h) break;   // uniform
             const int64_t R = w.r0 + rr;
-            const bool rin = R >= 0 && R < J.H;
+            const bool rin = bnd != kBoundZero || (R >= 0 && R < J.H);
             T v[KC];
 #pragma unroll
             for (int k = 0; k < KC; ++k) v[k] = A::from((rin && colin[k]) ? (double)ring[d][k] : 0.0);

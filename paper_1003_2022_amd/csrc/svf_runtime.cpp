@@ -80,6 +80,8 @@ svf_status check_opts(svf_ctx *ctx, const svf_opts *o, int T)
         return fail(ctx, SVF_EINVAL, "opts.max_reach_px must be in [1, %d] for tile %d", capmax, T);
     if (o->bands < 0 || o->bands > svf_ctx::kMaxBands)
         return fail(ctx, SVF_EINVAL, "opts.bands must be in [0, %d]", svf_ctx::kMaxBands);
+    if (o->boundary < SVF_BOUNDARY_ZERO || o->boundary > SVF_BOUNDARY_SYMMETRIC)
+        return fail(ctx, SVF_EINVAL, "opts.boundary must be 0..2");
     return SVF_OK;
 }
 
@@ -240,6 +242,7 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
     j.inv_sqrt_m = (float)(1.0 / std::sqrt((double)order));
     j.inv_sqrt_m_d = 1.0 / std::sqrt((double)order);
     j.fd_fp32 = o->fd_fp32 ? 1 : 0;
+    j.boundary = o->boundary;
     j.eps_full = o->eps_px2 * order;
     j.preint = o->preint;
     j.tr0 = 0;
@@ -280,6 +283,7 @@ void svf_default_opts(svf_opts *o)
     o->eps_px2 = kDefaultEps;
     o->tile = 0;
     o->max_reach_px = kDefaultCap;
+    o->boundary = SVF_BOUNDARY_ZERO;
 }
 
 svf_status svf_create(svf_ctx **out, int device, size_t hbm_budget_bytes)
@@ -477,7 +481,9 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
     } else {
         // Bands of tile rows on internal streams.  Pass p of band b reads pass p-1's
         // output on its windows, which reach at most cap + 5 rows beyond the band:
-        // it waits for pass p-1 of every band those rows touch.
+        // it waits for pass p-1 of every band those rows touch.  Under the replicate
+        // and mirror rules rows beyond a border read rows next to it: rows [lo, 0)
+        // read inside [0, -lo), rows [H, hi) inside [2H - hi, H).
         st = ensure_bands(ctx, nb, order);
         if (st) return st;
         std::vector<int> tr(nb + 1);
@@ -496,7 +502,12 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
             for (int b = 0; b < nb; ++b) {
                 hipStream_t sb = ctx->band_stream[b];
                 if (pass > 0) {
-                    const int64_t lo = (int64_t)tr[b] * p.T - halo, hi = (int64_t)tr[b + 1] * p.T + halo;
+                    int64_t lo = (int64_t)tr[b] * p.T - halo, hi = (int64_t)tr[b + 1] * p.T + halo;
+                    if (o.boundary != SVF_BOUNDARY_ZERO) {
+                        const int64_t H = in->H, lo0 = lo;
+                        if (hi > H) lo = std::min(lo, std::max<int64_t>(0, 2 * H - hi));
+                        if (lo0 < 0) hi = std::max(hi, std::min<int64_t>(H, -lo0));
+                    }
                     for (int o2 = 0; o2 < nb; ++o2) {
                         if (o2 == b || (int64_t)tr[o2 + 1] * p.T <= lo || (int64_t)tr[o2] * p.T >= hi) continue;
                         e = hipStreamWaitEvent(sb, ev(pass - 1, o2), 0);
