@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, by ``__graft_entry__.smoke()``
 and by the CPU-baseline leg of ``bench.py``.  The product package never imports
 it.  The arithmetic lives in ``svf_oracle.c`` (plain C, binary64); this module
-only marshals numpy arrays, composes passes and gathers boundary extensions.
+marshals numpy arrays, composes passes and gathers boundary extensions; the
+structure-tensor step is numpy in binary64.
 
 What it computes (Chaudhury, Munoz-Barrutia, Unser, "Fast space-variant
 elliptical filtering using box splines"):
@@ -19,7 +20,12 @@ elliptical filtering using box splines"):
   ZP interpolation) or with the direct sum  sum_k f[k] beta^4_{a(n)}(n - k).
 * ``filter_region(...)`` -- the same on a sub-rectangle of a large image (for
   sampled parity checks), pulling in only the region every pass depends on.
-* ``boundary`` (both) -- what each pass reads outside the image: zero, the
+* ``gradient``, ``structure_tensor``, ``st_triple``, ``st_field``,
+  ``smooth_adaptive`` -- the feature-preserving smoothing of Sec. 4.2: the
+  structure tensor J = w * (g g^T), the triple (s*, rho*, theta*) from its
+  eigen-decomposition (numpy.linalg.eigh) by the printed rules, and the filter
+  driven by it.
+* ``boundary`` (all) -- what each pass reads outside the image: zero, the
   nearest pixel, or the half-sample mirror; the recursion of Sec. 2.1 needs some
   such condition and the paper does not fix one.  Each pass then is the direct
   sum over the image extended by ``boundary_index``.
@@ -351,3 +357,93 @@ def filter_region(img: np.ndarray, field: np.ndarray, kind: int, order: int, rec
         out = _pass_rule(cur_img, fr0, fc0, H, W, a_for(rr), r0, c0, method, tile, boundary)
         cur_img, fr0, fc0 = out, r0, c0
     return cur_img
+
+
+# ----------------------------------------------------------------------------- structure tensor (Sec. 4.2)
+#
+# The application of Sec. 4.2 estimates the filter at every pixel from the
+# image itself: the structure tensor J = w * (g g^T) with g the gradient and w
+# an isotropic averaging window; theta* is the direction of the eigenvector of
+# the smallest eigenvalue of J (the direction of least intensity variation, along
+# which the filter is elongated); rho* and s* follow the printed rules on the two
+# eigenvalues.  Readings (the paper refers elsewhere for the details):
+# * g: central differences, g1 along x (columns), g2 along y (rows), the image
+#   extended by the boundary rule; several channels add their g g^T;
+# * w: the isotropic four-directional box spline of covariance sigma_w^2 I
+#   (all scales sigma_w sqrt 6, Thm. 2.2), iterated order_w times (Sec. 3.3),
+#   applied by this oracle's own filter with the same boundary rule;
+# * gain: the rules act on gain * J (gain 1: the eigenvalues in the image's units,
+#   as printed); an eigenvalue <= lambda_zero counts as zero;
+# * both eigenvalues zero: the isotropic box spline with all scales a_flat.
+
+
+def gradient(img: np.ndarray, boundary: int = BOUNDARY_ZERO):
+    """Central differences (g1 along columns, g2 along rows) in binary64, per channel."""
+    f = np.asarray(img, dtype=np.float64)
+    if f.ndim == 2:
+        f = f[..., None]
+    H, W = f.shape[:2]
+    if boundary == BOUNDARY_ZERO:
+        e = np.zeros((H + 2, W + 2, f.shape[2]))
+        e[1:-1, 1:-1] = f
+    else:
+        ri = boundary_index(np.arange(-1, H + 1), H, boundary)
+        ci = boundary_index(np.arange(-1, W + 1), W, boundary)
+        e = f[np.ix_(ri, ci)]
+    g1 = 0.5 * (e[1:-1, 2:] - e[1:-1, :-2])
+    g2 = 0.5 * (e[2:, 1:-1] - e[:-2, 1:-1])
+    return g1, g2
+
+
+def structure_tensor(img: np.ndarray, sigma_w: float, order_w: int = 1, boundary: int = BOUNDARY_ZERO,
+                     method: str = "fast", tile: int = 32) -> np.ndarray:
+    """J = w * (sum over channels of g g^T), (H, W, 3) = (J11, J12, J22), binary64."""
+    g1, g2 = gradient(img, boundary)
+    P = np.stack([(g1 * g1).sum(-1), (g1 * g2).sum(-1), (g2 * g2).sum(-1)], -1)
+    H, W = P.shape[:2]
+    a = np.broadcast_to(np.full(4, sigma_w * np.sqrt(6.0)) / np.sqrt(order_w), (H, W, 4))
+    return np.stack([filter_scales(P[..., k], np.ascontiguousarray(a), order_w, method, tile, boundary)
+                     for k in range(3)], -1)
+
+
+def st_triple(J: np.ndarray, gain: float = 1.0, lambda_zero: float = 0.0, a_flat: float = 1.0):
+    """(s*, rho*, theta*) per pixel from J (..., 3) by the rules of Sec. 4.2.
+
+    Eigen-decomposition by numpy.linalg.eigh; theta* in [0, pi).  Returns three
+    arrays (s, rho, theta); flat pixels get s = a_flat^2 / 3 (the size of the
+    box spline with all scales a_flat: covariance a_flat^2 / 6 I), rho = 1, theta = 0.
+    """
+    J = gain * np.asarray(J, dtype=np.float64)
+    M = np.stack([np.stack([J[..., 0], J[..., 1]], -1), np.stack([J[..., 1], J[..., 2]], -1)], -2)
+    lam, vec = np.linalg.eigh(M)            # ascending eigenvalues, eigenvectors in columns
+    lmin, lmax = lam[..., 0], lam[..., 1]
+    zmin, zmax = lmin <= lambda_zero, lmax <= lambda_zero
+    vmin = vec[..., :, 0]
+    theta = np.mod(np.arctan2(vmin[..., 1], vmin[..., 0]), np.pi)
+    lmin_eff = np.where(zmin, 0.0, lmin)
+    lmax_eff = np.where(zmax, 0.0, lmax)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rho = np.where(~zmin & ~zmax, lmax_eff / np.where(zmin, 1.0, lmin_eff), 1.0)
+    one = zmin & ~zmax                      # only the larger eigenvalue is non-zero
+    rho = np.where(one, np.maximum(1.0, lmax_eff), rho)
+    s = lmax_eff + lmin_eff
+    flat = zmin & zmax
+    s = np.where(flat, a_flat * a_flat / 3.0, s)
+    rho = np.where(flat, 1.0, rho)
+    theta = np.where(flat, 0.0, theta)
+    return s, rho, theta
+
+
+def st_field(img: np.ndarray, sigma_w: float, order_w: int = 1, gain: float = 1.0, lambda_zero: float = 0.0,
+             a_flat: float = 1.0, boundary: int = BOUNDARY_ZERO) -> np.ndarray:
+    """The (sigma, rho, theta) field (H, W, 3) float32 that drives the filter: sigma = sqrt(s / 2)."""
+    J = structure_tensor(img, sigma_w, order_w, boundary)
+    s, rho, theta = st_triple(J, gain, lambda_zero, a_flat)
+    return np.stack([np.sqrt(s / 2.0), rho, theta], -1).astype(np.float32)
+
+
+def smooth_adaptive(img: np.ndarray, sigma_w: float, order_w: int, gain: float, lambda_zero: float, a_flat: float,
+                    order: int, boundary: int = BOUNDARY_ZERO, eps: float = DEFAULT_EPS):
+    """Feature-preserving smoothing of Sec. 4.2: the structure-tensor field, then the order-m filter."""
+    fld = st_field(img, sigma_w, order_w, gain, lambda_zero, a_flat, boundary)
+    return filter(img, fld, FIELD_SRT3, order, eps, boundary=boundary)

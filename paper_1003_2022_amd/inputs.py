@@ -9,6 +9,9 @@ Workloads follow the paper's experiments (Sec. 4.1, Table 2: a 512x512 image
 filtered with kernels of several sizes) and the build's parity/bench configs:
 
 * images: FP32 uniform [0, 1) or uint16 uniform {0..65535};
+* noisy oriented images (the feature-preserving smoothing of Sec. 4.2:
+  stripes whose orientation and period vary smoothly, plus Gaussian noise,
+  optionally with a noise-free flat rectangle);
 * fields: per-pixel (sigma, rho, theta) with sigma = isotropic standard
   deviation in pixels, rho = elongation (variance ratio lambda_max/lambda_min,
   Sec. 3.2.1 descriptor D1), theta = orientation of the major axis in [0, pi),
@@ -26,6 +29,7 @@ __all__ = [
     "srt_field",
     "scales_field",
     "constant_srt_field",
+    "oriented_image",
 ]
 
 
@@ -116,3 +120,34 @@ def scales_field(h: int, w: int, seed: int, lo: float = 0.6, hi: float = 3.0, sm
     else:
         u = rng.random((h, w, 4))
     return np.ascontiguousarray((lo + u * (hi - lo)).astype(np.float32))
+
+
+def oriented_image(h: int, w: int, seed: int, period=(6.0, 14.0), amplitude: float = 0.4, noise: float = 0.1,
+                   corr_len: float | None = None, flat_box=None, dtype: str = "f32", channels: int = 1) -> np.ndarray:
+    """Noisy stripes: 0.5 + amplitude cos(2 pi (x cos t + y sin t) / period) + noise.
+
+    The orientation t and the period vary smoothly (correlation length corr_len,
+    default max(h, w) / 8); the noise is white Gaussian (std `noise`, drawn per
+    channel).  flat_box = (r0, c0, rh, rw) sets that rectangle to 0.5 exactly (no
+    stripes, no noise).  uint16 images map [0, 1] to {0..65535} (rounded, clipped).
+    """
+    if corr_len is None:
+        corr_len = max(4.0, max(h, w) / 8.0)
+    rng = np.random.default_rng(seed + 3_333_333)
+    n1 = _gauss_smooth_periodic(rng.standard_normal((h, w)), corr_len)
+    n2 = _gauss_smooth_periodic(rng.standard_normal((h, w)), corr_len)
+    t = 0.5 * np.arctan2(n2, n1)
+    lam = period[0] + smooth_uniform_field(h, w, rng, corr_len) * (period[1] - period[0])
+    y, x = np.mgrid[0:h, 0:w].astype(np.float64)
+    base = 0.5 + amplitude * np.cos(2.0 * np.pi * (x * np.cos(t) + y * np.sin(t)) / lam)
+    chans = []
+    for _ in range(channels):
+        f = base + noise * rng.standard_normal((h, w))
+        if flat_box is not None:
+            r0, c0, rh, rw = flat_box
+            f[r0:r0 + rh, c0:c0 + rw] = 0.5
+        chans.append(f)
+    f = chans[0] if channels == 1 else np.stack(chans, axis=-1)
+    if dtype == "u16":
+        return np.ascontiguousarray(np.clip(np.rint(f * 65535.0), 0, 65535).astype(np.uint16))
+    return np.ascontiguousarray(f.astype(np.float32))
