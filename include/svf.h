@@ -197,6 +197,57 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
 svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
                             const svf_opts *opts, svf_image *out, hipStream_t stream, int use_graph);
 
+/* ---- feature-preserving smoothing (Sec. 4.2) ----
+ *
+ * The filter at every pixel is estimated from the image: the structure tensor
+ * J = w * (g g^T), g the gradient, w an isotropic averaging window; theta* is
+ * the direction of the eigenvector of the smaller eigenvalue of J (least
+ * intensity variation, along the image features); with lmax >= lmin the
+ * eigenvalues of gain * J: rho* = lmax / lmin if both are non-zero, 1 if both
+ * are zero, max(1, lmax) if only lmax is; s* = lmax + lmin (a zero one counting
+ * as 0).  Flat pixels (both zero) get the isotropic box spline with all scales
+ * a_flat.  Details the paper leaves open, fixed here: g by central differences
+ * (g1 along columns, g2 along rows; the neighbours of border pixels follow
+ * opts->boundary); channels add their g g^T; w is the isotropic box spline of
+ * covariance sigma_w^2 I (scales sigma_w sqrt 6, Thm. 2.2) iterated order_w
+ * times and applied by the filter itself with opts (its pre-integration is
+ * never SVF_PRE_I64: SVF_PRE_F64 then); gain scales J before the rules.
+ */
+typedef struct {
+    double sigma_w;      /* window standard deviation, px (> 0; default 2) */
+    int32_t order_w;     /* window passes 1..3 (default 1) */
+    int32_t reserved;
+    double gain;         /* the rules act on gain * J (> 0; default 1: the image's own units) */
+    double lambda_zero;  /* an eigenvalue <= lambda_zero counts as zero (>= 0; default 0) */
+    double a_flat;       /* box scales of the flat-pixel filter, px (> 0; default 1) */
+} svf_st_params;
+
+/* Fill p with the defaults listed above. */
+void svf_st_default_params(svf_st_params *p);
+
+/*
+ * Structure tensor and the field it implies, for an image `in` (SVF_F32 or
+ * SVF_U16, 1..4 channels, values taken as they are).  tensor_out (device, may
+ * be NULL): (J11, J12, J22) float32 per pixel, rows tensor_row_stride floats
+ * apart (>= 3 W), J not scaled by gain.  field_out (device, may be NULL, not
+ * both): the SVF_FIELD_SRT3 field (sigma = sqrt(s* / 2), rho*, theta* in
+ * [0, pi)), rows field_row_stride floats apart (>= 3 W).  Needs a workspace of
+ * 12 B per pixel (24 if tensor_out is NULL) plus the filter's own for a
+ * 3-channel image (svf_workspace_bytes).  Returns after enqueueing.
+ */
+svf_status svf_structure_tensor(svf_ctx *ctx, const svf_image *in, const svf_st_params *params,
+                                const svf_opts *opts, float *tensor_out, int64_t tensor_row_stride,
+                                float *field_out, int64_t field_row_stride, hipStream_t stream);
+
+/*
+ * The smoothing itself: svf_structure_tensor's field drives svf_filter of `in`
+ * (order 1..3, opts as for svf_filter, the same boundary rule throughout) into
+ * out (SVF_F32, in's shape).  Workspace: 24 B per pixel plus the larger of the
+ * two filters' own.  rep as for svf_filter (of the final filter).
+ */
+svf_status svf_smooth_adaptive(svf_ctx *ctx, const svf_image *in, const svf_st_params *params, int order,
+                               const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep);
+
 /* ---- serving loop ----
  * A scheduler thread owned by the context admits requests (images of any size,
  * each with its own field and order) in arrival order while they fit in a
@@ -261,8 +312,8 @@ svf_status svf_server_stop(svf_ctx *ctx);
  * library's kernels on the caller's stream. ---- */
 svf_status svf_set_timing(svf_ctx *ctx, int enable);
 /* Sum of event-measured durations (ms) and launch count of one kernel class
- * ("scale_map", "preint", "fd", "batch": a whole batch launch sequence) since the last reset; waits for the recorded
- * events.  reset != 0 clears the accumulators afterwards. */
+ * ("scale_map", "preint", "fd", "batch": a whole batch launch sequence, "st": the structure-tensor
+ * gradient and eigenvalue kernels) since the last reset; waits for the recorded events.  reset != 0 clears the accumulators afterwards. */
 svf_status svf_kernel_time(svf_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int reset);
 
 #ifdef __cplusplus

@@ -41,6 +41,11 @@ class svf_opts(C.Structure):
                 ("max_reach_px", C.c_int32), ("bands", C.c_int32), ("boundary", C.c_int32)]
 
 
+class svf_st_params(C.Structure):
+    _fields_ = [("sigma_w", C.c_double), ("order_w", C.c_int32), ("reserved", C.c_int32), ("gain", C.c_double),
+                ("lambda_zero", C.c_double), ("a_flat", C.c_double)]
+
+
 class svf_report(C.Structure):
     _fields_ = [("clamped_px", C.c_int64), ("eps_active_px", C.c_int64), ("invalid_px", C.c_int64),
                 ("overflow_px", C.c_int64), ("max_reach_px", C.c_double)]
@@ -97,6 +102,14 @@ def lib() -> C.CDLL:
     L.svf_filter.argtypes = [vp, P(svf_image), P(svf_field), C.c_int, C.c_int, P(svf_opts), P(svf_image), vp, P(svf_report)]
     L.svf_filter_batch.restype = st
     L.svf_filter_batch.argtypes = [vp, C.c_int, P(svf_image), P(svf_field), P(C.c_int), P(svf_opts), P(svf_image), vp, C.c_int]
+    L.svf_st_default_params.restype = None
+    L.svf_st_default_params.argtypes = [P(svf_st_params)]
+    L.svf_structure_tensor.restype = st
+    L.svf_structure_tensor.argtypes = [vp, P(svf_image), P(svf_st_params), P(svf_opts), vp, C.c_int64, vp, C.c_int64,
+                                       vp]
+    L.svf_smooth_adaptive.restype = st
+    L.svf_smooth_adaptive.argtypes = [vp, P(svf_image), P(svf_st_params), C.c_int, P(svf_opts), P(svf_image), vp,
+                                      P(svf_report)]
     L.svf_set_timing.restype = st
     L.svf_set_timing.argtypes = [vp, C.c_int]
     L.svf_kernel_time.restype = st
@@ -248,6 +261,44 @@ def svf_filter_batch(ctx: Context, imgs, fields, orders, opts: svf_opts | None, 
     return ctx.check(lib().svf_filter_batch(ctx.ptr, n, IA(*imgs), FA(*fields), RA(*orders),
                                             C.byref(opts) if opts else None, OA(*outs), _stream_handle(stream),
                                             1 if use_graph else 0))
+
+
+def st_params(**kw) -> svf_st_params:
+    """svf_st_default_params, then the given fields."""
+    p = svf_st_params()
+    lib().svf_st_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def svf_structure_tensor(ctx: Context, img: svf_image, params: svf_st_params, opts: svf_opts | None, tensor_out=None,
+                         field_out=None, stream=None):
+    """tensor_out / field_out: float32 (H, W, 3) device tensors or None."""
+    def ptr_rs(t):
+        if t is None:
+            return None, 0
+        if t.dim() != 3 or t.shape[2] != 3 or t.stride(2) != 1 or t.stride(1) != 3:
+            raise ValueError("outputs are (H, W, 3) float32 with contiguous pixels")
+        return t.data_ptr(), t.stride(0)
+
+    tp, trs = ptr_rs(tensor_out)
+    fp, frs = ptr_rs(field_out)
+    return ctx.check(lib().svf_structure_tensor(ctx.ptr, C.byref(img), C.byref(params),
+                                                C.byref(opts) if opts else None, tp, trs, fp, frs,
+                                                _stream_handle(stream)))
+
+
+def svf_smooth_adaptive(ctx: Context, img: svf_image, params: svf_st_params, order: int, opts: svf_opts | None,
+                        out: svf_image, stream=None, report: bool = False):
+    rep = svf_report() if report else None
+    st = lib().svf_smooth_adaptive(ctx.ptr, C.byref(img), C.byref(params), order, C.byref(opts) if opts else None,
+                                   C.byref(out), _stream_handle(stream), C.byref(rep) if rep is not None else None)
+    if report:
+        return st, rep
+    return ctx.check(st)
 
 
 def svf_set_timing(ctx: Context, enable: bool):

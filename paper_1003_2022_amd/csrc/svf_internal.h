@@ -73,6 +73,44 @@ struct Window {
     int32_t h, w;
 };
 
+// Image index whose value lattice index i (possibly outside [0, N)) takes in a
+// pass input.  Zero rule: any in-range index (the value is masked to zero by the
+// caller).  Replicate: the nearest index.  Symmetric: the half-sample mirror
+// f[-1 - i] = f[i], f[2N - 1 - i] = f[i] (period 2N; small images reflect
+// several times).
+__device__ __forceinline__ int64_t ext_index(int64_t i, int64_t N, int b)
+{
+    if (b == kBoundSymmetric) {
+        if (i < 0) i = -1 - i;
+        if (i >= N) {   // rare: only windows that cross the far border
+            const int n2 = 2 * (int)N;
+            int m = (int)i % n2;   // i < N + 2 * kMaxWindow: fits in 32 bits
+            if (m >= (int)N) m = n2 - 1 - m;
+            i = m;
+        }
+        return i;
+    }
+    return min(max(i, (int64_t)0), N - 1);
+}
+
+// Structure-tensor step (svf_st.hip).  Image geometry of one call.
+struct StImage {
+    const void *in;
+    int64_t in_rs;           // elements between rows
+    int32_t in_type;         // InType
+    int32_t C;               // channels
+    int64_t H, W;
+    int32_t boundary;        // Boundary (the gradient's neighbours)
+    int32_t pad;
+};
+// P = sum over channels of (g1^2, g1 g2, g2^2), central differences; float32, 3 per pixel
+hipError_t launch_st_outer(const StImage &im, float *P, int64_t p_rs, hipStream_t s);
+// J (3 per pixel) -> (sigma, rho, theta) by the eigenvalue rules
+hipError_t launch_st_field(const float *J, int64_t j_rs, int64_t H, int64_t W, double gain, double lambda_zero,
+                           double a_flat, float *F, int64_t f_rs, hipStream_t s);
+// fill n float4 with v
+hipError_t launch_fill_f4(float *p, float4 v, int64_t n, hipStream_t s);
+
 // Host-side launchers (defined in svf_kernels.hip).  All enqueue on `s`.
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_scale_map(const Job &j, hipStream_t s);

@@ -63,26 +63,6 @@ __device__ __forceinline__ Window window_of(const Job &J, int tile)
     return w;
 }
 
-// Image index whose value lattice index i (possibly outside [0, N)) takes in a
-// pass input.  Zero rule: any in-range index (the value is masked to zero by the
-// caller).  Replicate: the nearest index.  Symmetric: the half-sample mirror
-// f[-1 - i] = f[i], f[2N - 1 - i] = f[i] (period 2N; small images reflect
-// several times).
-__device__ __forceinline__ int64_t ext_index(int64_t i, int64_t N, int b)
-{
-    if (b == kBoundSymmetric) {
-        if (i < 0) i = -1 - i;
-        if (i >= N) {   // rare: only windows that cross the far border
-            const int n2 = 2 * (int)N;
-            int m = (int)i % n2;   // i < N + 2 * kMaxWindow: fits in 32 bits
-            if (m >= (int)N) m = n2 - 1 - m;
-            i = m;
-        }
-        return i;
-    }
-    return min(max(i, (int64_t)0), N - 1);
-}
-
 // XCD-aware block order: consecutive hardware work-group ids go round-robin over
 // the 8 XCDs; remap so that each XCD receives one contiguous range of logical
 // blocks (the blocks of a tile share its window in that XCD's L2).

@@ -23,7 +23,7 @@ constexpr double kDefaultEps = 0.25;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-const char *kClassNames[kNumKernelClasses] = {"scale_map", "preint", "fd", "batch"};
+const char *kClassNames[kNumKernelClasses] = {"scale_map", "preint", "fd", "batch", "st"};
 
 }  // namespace
 
@@ -434,11 +434,22 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
         return fail(ctx, SVF_EUNSUPPORTED, "integer pre-integration needs a uint16 image");
     if (rep) std::memset(rep, 0, sizeof *rep);
     if (in->H == 0 || in->W == 0) return SVF_OK;
+    return svf::run_filter(ctx, in, field, order, o, out, stream, rep, 0);
+}
+
+}  // extern "C"
+
+// The filter proper on checked arguments, its workspace at ctx->ws + ws_off
+// (callers that keep their own buffers at the front of the workspace grow it to
+// ws_off + plan bytes first).
+svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
+                           svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off)
+{
     Plan p = plan_for(in, order, &o);
-    st = ensure_workspace(ctx, p.bytes);
+    svf_status st = ensure_workspace(ctx, ws_off + p.bytes);
     if (st) return st;
     hipSetDevice(ctx->device);
-    unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
+    unsigned char *ws = static_cast<unsigned char *>(ctx->ws) + ws_off;
     Job j = base_job(in, field, order, &o, p, ws);
     j.out = static_cast<float *>(out->data);
     j.out_rs = out->row_stride;
@@ -542,6 +553,8 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
     }
     return SVF_OK;
 }
+
+extern "C" {
 
 svf_status svf_set_timing(svf_ctx *ctx, int enable)
 {

@@ -11,7 +11,7 @@
 #include "svf.h"
 #include "svf_internal.h"
 
-enum { kClsScaleMap = 0, kClsPreint = 1, kClsFd = 2, kClsBatch = 3, kNumKernelClasses = 4 };
+enum { kClsScaleMap = 0, kClsPreint = 1, kClsFd = 2, kClsBatch = 3, kClsSt = 4, kNumKernelClasses = 5 };
 
 struct svf_ctx {
     int device = 0;
@@ -61,6 +61,8 @@ svf_status ensure_pinned(svf_ctx *ctx, size_t bytes);
 void fill_report(const TileStat *ts, size_t nt, int order, svf_report *rep);
 Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
              unsigned char *ws);
+svf_status run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
+                      svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off);
 
 }  // namespace svf
 

@@ -1,0 +1,150 @@
+// svf_st.hip -- gfx950 kernels of the structure-tensor step of the
+// feature-preserving smoothing (Sec. 4.2):
+//
+//   k_st_outer : g = central differences of the image (each channel), written as
+//                P = sum_c (g1^2, g1 g2, g2^2), three floats per pixel.  The
+//                window w * P is then the ordinary filter (isotropic box spline,
+//                constant scales) run by the runtime on P as a 3-channel image.
+//   k_st_field : J -> (sigma, rho, theta): the eigen-decomposition of gain * J in
+//                closed form and the printed rules; theta is the direction of the
+//                eigenvector of the smaller eigenvalue, sigma = sqrt(s / 2).
+//
+// Both are one pass over HBM per pixel (no reuse beyond the four neighbours of
+// the differences, which the L1/L2 serve): 64 x 4 pixel blocks, coalesced rows.
+
+#include <hip/hip_runtime.h>
+
+#include "svf_internal.h"
+
+namespace svf {
+namespace {
+
+constexpr int kStCols = 64, kStRows = 4;
+
+template <int IN>
+__device__ __forceinline__ double st_load(const StImage &im, int64_t r, int64_t c, int ch)
+{
+    // neighbour (r, c) of the differences: the boundary rule outside the image
+    // (zero rule: the value 0)
+    if (im.boundary == kBoundZero && (r < 0 || r >= im.H || c < 0 || c >= im.W)) return 0.0;
+    const int64_t R = ext_index(r, im.H, im.boundary), C = ext_index(c, im.W, im.boundary);
+    if (IN == kInF32) return (double)static_cast<const float *>(im.in)[R * im.in_rs + C * im.C + ch];
+    return (double)static_cast<const unsigned short *>(im.in)[R * im.in_rs + C * im.C + ch];
+}
+
+template <int IN>
+__global__ __launch_bounds__(kStCols *kStRows) void k_st_outer(StImage im, float *P, int64_t p_rs, int nbx,
+                                                               int64_t nblocks)
+{
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int64_t by = b / nbx, bx = b - by * nbx;
+        const int64_t r = by * kStRows + (threadIdx.x >> 6), c = bx * kStCols + (threadIdx.x & 63);
+        if (r >= im.H || c >= im.W) continue;
+        double p11 = 0.0, p12 = 0.0, p22 = 0.0;
+        for (int ch = 0; ch < im.C; ++ch) {
+            const double g1 = 0.5 * (st_load<IN>(im, r, c + 1, ch) - st_load<IN>(im, r, c - 1, ch));
+            const double g2 = 0.5 * (st_load<IN>(im, r + 1, c, ch) - st_load<IN>(im, r - 1, c, ch));
+            p11 += g1 * g1;
+            p12 += g1 * g2;
+            p22 += g2 * g2;
+        }
+        float *o = P + r * p_rs + c * 3;
+        o[0] = (float)p11;
+        o[1] = (float)p12;
+        o[2] = (float)p22;
+    }
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+__global__ __launch_bounds__(kStCols *kStRows) void k_st_field(const float *J, int64_t j_rs, int64_t H, int64_t W,
+                                                               double gain, double lambda_zero, double a_flat,
+                                                               float *F, int64_t f_rs, int nbx, int64_t nblocks)
+{
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int64_t by = b / nbx, bx = b - by * nbx;
+        const int64_t r = by * kStRows + (threadIdx.x >> 6), c = bx * kStCols + (threadIdx.x & 63);
+        if (r >= H || c >= W) continue;
+        const float *jp = J + r * j_rs + c * 3;
+        const double a = gain * (double)jp[0], bb = gain * (double)jp[1], cc = gain * (double)jp[2];
+        // eigenvalues of [[a, b], [b, c]]: the larger from the trace and the
+        // discriminant, the smaller as det / larger (no cancellation)
+        const double dif = a - cc;
+        const double disc = sqrt(dif * dif + 4.0 * bb * bb);
+        const double lmax = 0.5 * ((a + cc) + disc);
+        const double lmin = lmax > 0.0 ? (a * cc - bb * bb) / lmax : 0.5 * ((a + cc) - disc);
+        const bool zmax = !(lmax > lambda_zero), zmin = !(lmin > lambda_zero);
+        double s, rho, theta;
+        if (zmax && zmin) {   // locally flat: isotropic box spline with all scales a_flat
+            s = a_flat * a_flat / 3.0;
+            rho = 1.0;
+            theta = 0.0;
+        } else {
+            // eigenvector of the larger eigenvalue at 0.5 atan2(2b, a - c); the
+            // filter's major axis is the other one
+            theta = 0.5 * atan2(2.0 * bb, dif) + 0.5 * kPi;
+            if (theta >= kPi) theta -= kPi;
+            if (theta < 0.0) theta += kPi;
+            if (zmin) {   // only the larger eigenvalue is non-zero
+                s = lmax;
+                rho = fmax(1.0, lmax);
+            } else {
+                s = lmax + lmin;
+                rho = lmax / lmin;
+            }
+        }
+        float *o = F + r * f_rs + c * 3;
+        o[0] = (float)sqrt(0.5 * s);
+        o[1] = (float)rho;
+        o[2] = (float)theta;
+    }
+}
+
+__global__ void k_fill_f4(float4 *p, float4 v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int64_t st_blocks(int64_t H, int64_t W, int *nbx)
+{
+    *nbx = (int)((W + kStCols - 1) / kStCols);
+    return (int64_t)*nbx * ((H + kStRows - 1) / kStRows);
+}
+
+}  // namespace
+
+hipError_t launch_st_outer(const StImage &im, float *P, int64_t p_rs, hipStream_t s)
+{
+    int nbx;
+    const int64_t nb = st_blocks(im.H, im.W, &nbx);
+    if (nb == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(nb, 1 << 20);
+    if (im.in_type == kInF32)
+        hipLaunchKernelGGL(k_st_outer<kInF32>, dim3(grid), dim3(kStCols * kStRows), 0, s, im, P, p_rs, nbx, nb);
+    else
+        hipLaunchKernelGGL(k_st_outer<kInU16>, dim3(grid), dim3(kStCols * kStRows), 0, s, im, P, p_rs, nbx, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_st_field(const float *J, int64_t j_rs, int64_t H, int64_t W, double gain, double lambda_zero,
+                           double a_flat, float *F, int64_t f_rs, hipStream_t s)
+{
+    int nbx;
+    const int64_t nb = st_blocks(H, W, &nbx);
+    if (nb == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(nb, 1 << 20);
+    hipLaunchKernelGGL(k_st_field, dim3(grid), dim3(kStCols * kStRows), 0, s, J, j_rs, H, W, gain, lambda_zero,
+                       a_flat, F, f_rs, nbx, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f4(float *p, float4 v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_f4, dim3(grid), dim3(256), 0, s, reinterpret_cast<float4 *>(p), v, n);
+    return hipGetLastError();
+}
+
+}  // namespace svf
