@@ -24,9 +24,15 @@ Beside it, in the same JSON line:
                 uint16 input) and the FP32 finite difference on the same
                 workload: max and RMS relative error against the CPU FP64
                 oracle on sampled regions, and ms per step;
+  smoothing     the feature-preserving smoothing of Sec. 4.2 on a 4096 x 4096
+                noisy oriented FP32 image: structure tensor (window sigma_w 2 px),
+                the (s, rho, theta) field by the eigenvalue rules, then the
+                order-2 filter, mirror boundary; ms per step, per-kernel times,
+                and the error against the oracle on sampled regions;
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve] [--no-precision]
+                    [--no-smooth]
                     [--calib-copy] [--preint f64|f32c] [--tile T] [--qps Q] [--serve-seconds S]
 """
 from __future__ import annotations
@@ -298,6 +304,75 @@ def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, step_mpx=0, n_sat=120):
 PREC_REGIONS = [(0, 0, 96, 96), (2000, 2040, 96, 96), (4000, 3990, 96, 106)]
 
 
+ST_SIGMA_W, ST_GAIN = 2.0, 120.0
+# (r0, c0, h, w) of the output checked, inside a crop grown by ST_MARGIN px (clipped at the image)
+ST_REGIONS = [(0, 0, 96, 96), (2000, 3000, 96, 96), (4000, 4000, 96, 96)]
+ST_MARGIN = 64
+
+
+def smoothing_leg(P, I, ctx, torch, steps=5):
+    """svf_smooth_adaptive on a 4096^2 noisy oriented image: time, kernel split, error on sampled regions."""
+    import oracle
+
+    dev = torch.device("cuda:0")
+    img = I.oriented_image(H, W, SEED + 2, noise=0.1)
+    ti = torch.from_numpy(img).to(dev)
+    out = torch.empty_like(ti)
+    b = P.SVF_BOUNDARY_SYMMETRIC
+    prm = P.st_params(sigma_w=ST_SIGMA_W, gain=ST_GAIN, a_flat=1.0)
+    o = P.default_opts(boundary=b)
+    im_d, out_d = P.image_of(ti), P.image_of(out)
+    stream = torch.cuda.current_stream()
+    st, rep = P.svf_smooth_adaptive(ctx, im_d, prm, ORDER, o, out_d, stream, report=True)
+    for _ in range(2):
+        P.svf_smooth_adaptive(ctx, im_d, prm, ORDER, o, out_d, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        P.svf_smooth_adaptive(ctx, im_d, prm, ORDER, o, out_d, stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    P.svf_set_timing(ctx, True)
+    classes = ("st", "scale_map", "preint", "fd")
+    for k in classes:
+        P.svf_kernel_time(ctx, k, reset=True)
+    for _ in range(steps):
+        P.svf_smooth_adaptive(ctx, im_d, prm, ORDER, o, out_d, stream)
+    torch.cuda.synchronize()
+    kt = {k: P.svf_kernel_time(ctx, k) for k in classes}
+    P.svf_set_timing(ctx, False)
+    o_np = out.cpu().numpy()
+    oracle.build()
+    errs = []
+    t0 = time.perf_counter()
+    for (r0, c0, h, w) in ST_REGIONS:
+        R0, C0 = max(0, r0 - ST_MARGIN), max(0, c0 - ST_MARGIN)
+        R1, C1 = min(H, r0 + h + ST_MARGIN), min(W, c0 + w + ST_MARGIN)
+        ref = oracle.smooth_adaptive(img[R0:R1, C0:C1], ST_SIGMA_W, 1, ST_GAIN, 0.0, 1.0, ORDER, boundary=b)
+        errs.append(rel_errors(o_np[r0:r0 + h, c0:c0 + w], ref[r0 - R0:r0 - R0 + h, c0 - C0:c0 - C0 + w]))
+    mx = max(e[0] for e in errs)
+    rms = float(np.sqrt(np.mean([e[1] ** 2 for e in errs])))
+    log(f"smoothing: {ms:.3f} ms/step, {H * W / (ms * 1e-3) / 1e6:.1f} Mpixel/s; max rel {mx:.2e} rms {rms:.2e} "
+        f"(oracle {time.perf_counter() - t0:.1f} s)")
+    per_step = {k: round(tot / max(steps, 1), 4) for k, (tot, n) in kt.items()}
+    for k, (tot, n) in kt.items():
+        log(f"  smoothing {k}: {tot / max(n, 1) * 1e3:.1f} us avg over {n} launches")
+    return {
+        "workload": f"4096x4096 f32 noisy stripes (period 6-14 px, amplitude 0.4, noise std 0.1, seed {SEED + 2}); "
+                    f"structure tensor with sigma_w {ST_SIGMA_W} px (1 pass), gain {ST_GAIN}, then the order-{ORDER} "
+                    "filter; mirror boundary; FP64 pre-integration and finite difference",
+        "ms_per_step": round(ms, 3),
+        "Mpixel_s": round(H * W / (ms * 1e-3) / 1e6, 1),
+        "kernel_ms_per_step": per_step,
+        "kernel_avg_us": {k: round(tot / max(n, 1) * 1e3, 2) for k, (tot, n) in kt.items()},
+        "report": {"clamped_px": rep.clamped_px, "eps_active_px": rep.eps_active_px,
+                   "max_reach_px": round(rep.max_reach_px, 2)},
+        "max_rel": mx,
+        "rms_rel": rms,
+        "regions": ST_REGIONS,
+    }
+
+
 def rel_errors(got, ref):
     """Max and RMS of |got - ref| / max(|ref|, 1e-3 max|ref|) per pixel."""
     got = np.asarray(got, np.float64)
@@ -357,6 +432,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-variant leg")
+    ap.add_argument("--no-smooth", action="store_true", help="skip the feature-preserving smoothing leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
@@ -488,6 +564,8 @@ def main():
     }
     if not args.no_precision:
         line["precision"] = precision_leg(P, I, ctx, img, fld, ti, tf, torch)
+    if not args.no_smooth:
+        line["smoothing"] = smoothing_leg(P, I, ctx, torch)
     if not args.no_batch:
         line["batch"] = batch_leg(P, I, ctx, ti, torch)
     if not args.no_serve:

@@ -8,7 +8,9 @@ element by element:
 
 * 1024 x 1024 FP32, order 2, sigma 1-16 px, elongation 1-4 (correlation 64 px);
 * 4096 x 4096 FP32 and uint16, order 2, sigma 1-32 px, elongation 1-6
-  (correlation 256 px), every pre-integration variant.
+  (correlation 256 px), every pre-integration variant;
+* 4096 x 4096 feature-preserving smoothing (structure-tensor field, order 2),
+  mirror and replicate boundaries, on regions at the corners, edges and inside.
 
 Tolerance: |gpu - ref| <= 1e-5 max(|ref|, 1e-3 max|ref|) per pixel, RMS <= 1e-6
 (FP64 and int64 pre-integration); the compensated FP32 variant is held to the
@@ -113,3 +115,26 @@ def test_4096_fd_fp32_reported(ctx, big):
     assert np.isfinite(got).all()
     mx, rms = compare(got, img, fld, 2, REGIONS_4096[2:3], "4096^2 f32 fd_fp32", check=False)
     print(f"FP32 finite difference (comparison variant): max rel {mx:.2e} rms {rms:.2e}")
+
+
+@pytest.mark.parametrize("boundary", [P.SVF_BOUNDARY_SYMMETRIC, P.SVF_BOUNDARY_REPLICATE])
+def test_4096_smooth_adaptive(ctx, boundary):
+    # the smoothing leg's workload: noisy stripes, structure-tensor field, order 2; the
+    # oracle smooths a crop grown by 64 px around each region (clipped at the image:
+    # the crop's own border is then the image's, elsewhere it is beyond every reach)
+    H = W = 4096
+    img = I.oriented_image(H, W, 3002, noise=0.1)
+    ti = torch.from_numpy(img).to(DEV)
+    out = torch.empty_like(ti)
+    prm = P.st_params(sigma_w=2.0, gain=120.0, a_flat=1.0)
+    P.svf_smooth_adaptive(ctx, P.image_of(ti), prm, 2, P.default_opts(boundary=boundary), P.image_of(out))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for (r0, c0, h, w) in [(0, 0, 80, 80), (0, 2048, 40, 100), (1500, 4020, 90, 76), (4030, 4030, 66, 66)]:
+        R0, C0 = max(0, r0 - 64), max(0, c0 - 64)
+        R1, C1 = min(H, r0 + h + 64), min(W, c0 + w + 64)
+        ref = oracle.smooth_adaptive(img[R0:R1, C0:C1], 2.0, 1, 120.0, 0.0, 1.0, 2, boundary=boundary)
+        ref = ref[r0 - R0:r0 - R0 + h, c0 - C0:c0 - C0 + w]
+        mx, rms = rel(got[r0:r0 + h, c0:c0 + w], ref)
+        print(f"smooth 4096 boundary {boundary} region {(r0, c0, h, w)}: max rel {mx:.2e} rms {rms:.2e}", flush=True)
+        assert mx <= 1e-5 and rms <= 1e-6
