@@ -25,6 +25,8 @@ elliptical filtering using box splines"):
   structure tensor J = w * (g g^T), the triple (s*, rho*, theta*) from its
   eigen-decomposition (numpy.linalg.eigh) by the printed rules, and the filter
   driven by it.
+* ``lut_table``, ``scales_lut``, ``filter_lut`` -- the look-up-table scale map
+  of Sec. 3.2.2 (unit-size solutions over elongation and one octant, O1/O2).
 * ``boundary`` (all) -- what each pass reads outside the image: zero, the
   nearest pixel, or the half-sample mirror; the recursion of Sec. 2.1 needs some
   such condition and the paper does not fix one.  Each pass then is the direct
@@ -33,6 +35,7 @@ elliptical filtering using box splines"):
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from pathlib import Path
@@ -447,3 +450,88 @@ def smooth_adaptive(img: np.ndarray, sigma_w: float, order_w: int, gain: float, 
     """Feature-preserving smoothing of Sec. 4.2: the structure-tensor field, then the order-m filter."""
     fld = st_field(img, sigma_w, order_w, gain, lambda_zero, a_flat, boundary)
     return filter(img, fld, FIELD_SRT3, order, eps, boundary=boundary)
+
+
+# ----------------------------------------------------------------------------- scale look-up table (Sec. 3.2.2)
+#
+# The paper's alternative to a solve per pixel: tabulate the solution for unit
+# size, s = 1, over elongation and the orientations of one octant, then per pixel
+# (O1) reduce theta to phi in [0, pi/4) and its octant k, (O2) look up and
+# permute by k and scale by sqrt(s).  Readings: the table is over
+# u = 1 / rho in [0, 1] (u = 0: unbounded elongation, which the solve clamps)
+# and phi, nodes equally spaced, values float32, bilinear interpolation; the
+# permutation for octant k is the rotation of the scale vector by k places,
+# (a1, a2, a3, a4) -> (a4, a1, a2, a3) per quarter of a right angle (the printed
+# rows for the second and fourth octants are exchanged); the floor on a^2 is
+# relative, eps_rel * s, since the unit-size solution is scaled by sqrt(s).
+
+LUT_DEFAULT_NODES = 129
+LUT_DEFAULT_EPS_REL = 0.125
+
+
+def lut_table(nodes: int = LUT_DEFAULT_NODES, eps_rel: float = LUT_DEFAULT_EPS_REL) -> np.ndarray:
+    """(nodes, nodes, 4) float32: entry [i, j] solves s = 1, rho = (nodes-1)/i, phi = j pi / (4 (nodes-1))."""
+    T = np.empty((nodes, nodes, 4), dtype=np.float32)
+    sig1 = math.sqrt(0.5)   # s = 2 sigma^2 = 1
+    for i in range(nodes):
+        rho = (nodes - 1) / i if i > 0 else 1e300
+        for j in range(nodes):
+            a, _, _ = scales_from_srt(sig1, rho, j * (math.pi / 4) / (nodes - 1), eps_rel)
+            T[i, j] = a
+    return T
+
+
+def srt_of_field(field: np.ndarray, kind: int):
+    """(s, rho, theta, valid) per pixel from an SRT3 or COV3 field (float64)."""
+    f = np.asarray(field, dtype=np.float64)
+    if kind == FIELD_SRT3:
+        sig, rho, th = f[..., 0], f[..., 1], f[..., 2]
+        valid = np.isfinite(f).all(-1) & (sig > 0) & (rho >= 1)
+        return 2 * sig * sig, rho, th, valid
+    c11, c12, c22 = f[..., 0], f[..., 1], f[..., 2]
+    det = c11 * c22 - c12 * c12
+    valid = np.isfinite(f).all(-1) & (c11 > 0) & (c22 > 0) & (det > 0)
+    s = c11 + c22
+    dd = np.sqrt((c11 - c22) ** 2 + 4 * c12 * c12)
+    lmax, lmin = 0.5 * (s + dd), 0.5 * (s - dd)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rho = np.where(valid, lmax / np.where(lmin > 0, lmin, 1.0), 1.0)
+    return s, rho, 0.5 * np.arctan2(2 * c12, c11 - c22), valid
+
+
+def scales_lut(field: np.ndarray, kind: int, order: int = 1, nodes: int = LUT_DEFAULT_NODES,
+               eps_rel: float = LUT_DEFAULT_EPS_REL, table: np.ndarray | None = None) -> np.ndarray:
+    """Per-pass scales (H, W, 4) float64 by the look-up table (O1, O2); NaN where the field is invalid."""
+    T = lut_table(nodes, eps_rel).astype(np.float64) if table is None else np.asarray(table, np.float64)
+    n = T.shape[0]
+    s, rho, th, valid = srt_of_field(field, kind)
+    rho = np.where(valid, rho, 1.0)
+    s = np.where(valid, s, 1.0)
+    th = np.mod(np.where(valid, th, 0.0), math.pi)
+    k = np.clip(np.floor(th / (math.pi / 4)), 0, 3).astype(np.int64)
+    phi = th - k * (math.pi / 4)
+    fu = (1.0 / rho) * (n - 1)
+    fp = phi / (math.pi / 4) * (n - 1)
+    i0 = np.clip(np.floor(fu), 0, n - 2).astype(np.int64)
+    j0 = np.clip(np.floor(fp), 0, n - 2).astype(np.int64)
+    wu, wp = (fu - i0)[..., None], (fp - j0)[..., None]
+    a1 = ((1 - wu) * (1 - wp) * T[i0, j0] + (1 - wu) * wp * T[i0, j0 + 1]
+          + wu * (1 - wp) * T[i0 + 1, j0] + wu * wp * T[i0 + 1, j0 + 1])
+    out = np.empty_like(a1)
+    for q in range(4):   # octant q: the tabulated vector rotated by q places
+        m = k == q
+        out[m] = np.roll(a1[m], q, axis=-1)
+    out *= np.sqrt(s)[..., None]
+    out[~valid] = np.nan
+    return out / math.sqrt(order)
+
+
+def filter_lut(img: np.ndarray, field: np.ndarray, kind: int, order: int = 1, nodes: int = LUT_DEFAULT_NODES,
+               eps_rel: float = LUT_DEFAULT_EPS_REL, method: str = "fast", tile: int = 32,
+               boundary: int = BOUNDARY_ZERO):
+    """The filter with the look-up-table scale map."""
+    a = scales_lut(field, kind, order, nodes, eps_rel)
+    if img.ndim == 3:
+        return np.stack([filter_scales(img[..., ch], a, order, method, tile, boundary) for ch in range(img.shape[2])],
+                        -1)
+    return filter_scales(img, a, order, method, tile, boundary)
