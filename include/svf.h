@@ -101,6 +101,18 @@ typedef enum {
                                     (period 2N; an image narrower than the support reflects again) */
 } svf_boundary;
 
+/* From the field to the scale vector (Sec. 3.2.2). */
+typedef enum {
+    SVF_SCALE_SOLVE = 0,  /* the optimisation solved at every pixel (floor eps_px2 * order on a_k^2) */
+    SVF_SCALE_LUT = 1     /* the paper's table: unit-size solutions over u = 1/rho in [0, 1] and
+                             phi in [0, pi/4] (lut_nodes^2 nodes, built once per (nodes, floor) on
+                             the device and kept by the context); per pixel the octant k of theta,
+                             bilinear interpolation at (1/rho, theta - k pi/4), the vector rotated
+                             by k places ((a1,a2,a3,a4) -> (a4,a1,a2,a3) per octant) and scaled by
+                             sqrt(s).  The floor is relative (lut_eps_rel * s); the covariance
+                             error of the interpolation is ~1e-4 of s at 129 nodes. */
+} svf_scale_method;
+
 typedef struct {
     int32_t preint;       /* svf_preint, default SVF_PRE_F64 */
     int32_t fd_fp32;      /* 0: finite difference and interpolation in binary64 (default);
@@ -118,6 +130,10 @@ typedef struct {
                              same bit for bit. */
     int32_t boundary;     /* svf_boundary: what every pass reads outside the image (default
                              SVF_BOUNDARY_ZERO) */
+    int32_t scale_map;    /* svf_scale_method: how the field becomes scales (default SVF_SCALE_SOLVE) */
+    int32_t lut_nodes;    /* SVF_SCALE_LUT: nodes per table axis, 9..1025 (default 129) */
+    double lut_eps_rel;   /* SVF_SCALE_LUT: floor on a_k^2 relative to the size s, in (0, 1]
+                             (default 0.125); replaces eps_px2 */
 } svf_opts;
 
 typedef struct {

@@ -35,6 +35,7 @@ elliptical filtering using box splines"):
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import math
 import os
 import subprocess
@@ -471,6 +472,11 @@ LUT_DEFAULT_EPS_REL = 0.125
 
 def lut_table(nodes: int = LUT_DEFAULT_NODES, eps_rel: float = LUT_DEFAULT_EPS_REL) -> np.ndarray:
     """(nodes, nodes, 4) float32: entry [i, j] solves s = 1, rho = (nodes-1)/i, phi = j pi / (4 (nodes-1))."""
+    return _lut_table(int(nodes), float(eps_rel)).copy()
+
+
+@functools.lru_cache(maxsize=8)
+def _lut_table(nodes: int, eps_rel: float) -> np.ndarray:
     T = np.empty((nodes, nodes, 4), dtype=np.float32)
     sig1 = math.sqrt(0.5)   # s = 2 sigma^2 = 1
     for i in range(nodes):

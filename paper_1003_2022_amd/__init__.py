@@ -21,6 +21,7 @@ SVF_F32, SVF_U16 = 0, 1
 SVF_FIELD_COV3, SVF_FIELD_SRT3, SVF_FIELD_SCALES4 = 0, 1, 2
 SVF_PRE_F64, SVF_PRE_F32C, SVF_PRE_I64 = 0, 1, 2
 SVF_BOUNDARY_ZERO, SVF_BOUNDARY_REPLICATE, SVF_BOUNDARY_SYMMETRIC = 0, 1, 2
+SVF_SCALE_SOLVE, SVF_SCALE_LUT = 0, 1
 
 STATUS_NAMES = {0: "SVF_OK", 1: "SVF_EINVAL", 2: "SVF_EUNSUPPORTED", 3: "SVF_ENOMEM", 4: "SVF_EHIP",
                 5: "SVF_EBUSY", 6: "SVF_ECANCELLED", 7: "SVF_ERANGE"}
@@ -38,7 +39,8 @@ class svf_field(C.Structure):
 
 class svf_opts(C.Structure):
     _fields_ = [("preint", C.c_int32), ("fd_fp32", C.c_int32), ("eps_px2", C.c_double), ("tile", C.c_int32),
-                ("max_reach_px", C.c_int32), ("bands", C.c_int32), ("boundary", C.c_int32)]
+                ("max_reach_px", C.c_int32), ("bands", C.c_int32), ("boundary", C.c_int32),
+                ("scale_map", C.c_int32), ("lut_nodes", C.c_int32), ("lut_eps_rel", C.c_double)]
 
 
 class svf_st_params(C.Structure):

@@ -127,6 +127,9 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     svf_status st = ensure_workspace(ctx, pos);
     if (st) return st;
     hipSetDevice(ctx->device);
+    Job lutj;
+    st = attach_lut(ctx, o, lutj, stream);   // before any capture: the table is built once
+    if (st) return st;
     BatchState *B = state(ctx);
     if (B->generation != ctx->ws_generation) {
         drop_graphs(B);
@@ -172,6 +175,9 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         kc = std::max(kc, batch_chunks_for(p.T, p.cap));
         svf_opts oi = o;
         Job base = base_job(&in[i], &fields[i], orders[i], &oi, p, ws);
+        base.lut = lutj.lut;
+        base.lut_n = lutj.lut_n;
+        base.lut_eps = lutj.lut_eps;
         base.out = static_cast<float *>(out[i].data);
         base.out_rs = out[i].row_stride;
         base.smap_base = tot_smap;
@@ -199,7 +205,8 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     }
     {
         char buf[96];
-        snprintf(buf, sizeof buf, "#%d,%d,%.17g", o.preint, o.fd_fp32, o.eps_px2);
+        // the captured kernels depend on these (boundary and table live in the descriptors)
+        snprintf(buf, sizeof buf, "#%d,%d,%.17g,%d", o.preint, o.fd_fp32, o.eps_px2, o.scale_map);
         key += buf;
     }
     hipError_t e = hipMemcpyAsync(B->d_jobs, B->h_jobs, sizeof(Job) * kTables * B->cap, hipMemcpyHostToDevice, stream);
@@ -211,7 +218,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t r = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(fill_bytes / 4), s);
         if (r != hipSuccess) return r;
-        r = launch_scale_map_batch(B->d_jobs, counts[0], tot_smap, kPersistentScale, s);
+        r = launch_scale_map_batch(B->d_jobs, counts[0], tot_smap, kPersistentScale, lutj.lut != nullptr, s);
         if (r != hipSuccess) return r;
         for (int pass = 0; pass < max_order; ++pass) {
             for (int ch = 1; ch <= kMaxChannels; ++ch) {

@@ -65,6 +65,10 @@ struct Job {
     int32_t boundary;        // Boundary: what a pass reads outside the image
     // single-image launches cover the tile rows [tr0, tr1) (scale map: their pixel rows)
     int32_t tr0, tr1;
+    // look-up-table scale map (nullptr: the solve per pixel)
+    const float *lut;        // lut_n x lut_n float4, [i][j]: rho = (n-1)/i, phi = j pi / (4 (n-1)), s = 1
+    int32_t lut_n, pad2;
+    double lut_eps;          // the table's floor on a^2 at s = 1
 };
 
 // Rectangle of lattice samples pre-integrated for one tile.
@@ -114,6 +118,8 @@ hipError_t launch_fill_f4(float *p, float4 v, int64_t n, hipStream_t s);
 // Host-side launchers (defined in svf_kernels.hip).  All enqueue on `s`.
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_scale_map(const Job &j, hipStream_t s);
+// unit-size scale table for the look-up-table scale map (n x n float4)
+hipError_t launch_lut_build(float *lut, int n, double eps, hipStream_t s);
 hipError_t launch_preint(const Job &j, hipStream_t s);
 hipError_t launch_fd(const Job &j, hipStream_t s);
 // standalone pre-integration of a caller-given window (svf_preintegrate)
@@ -121,7 +127,7 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
                                 hipStream_t s);
 // batched: `jobs` is a device table of n jobs; totals are the sums of the per-job counts
 // (persistent: `grid` work-groups loop over the work list)
-hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, hipStream_t s);
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s);
 hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, int kc, hipStream_t s);
 hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,
                            hipStream_t s);

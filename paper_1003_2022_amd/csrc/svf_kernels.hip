@@ -218,6 +218,81 @@ __device__ bool solve_cov(double C11, double C12, double C22, double eps, double
     return true;
 }
 
+// Look-up-table scale map (Sec. 3.2.2, O1/O2): theta reduced to its octant k and
+// phi = theta - k pi/4, the unit-size table interpolated bilinearly at
+// (1/rho, phi), the vector rotated by k places ((a1,a2,a3,a4) -> (a4,a1,a2,a3)
+// per octant) and scaled by sqrt(s).  In binary32: the interpolation is
+// continuous across cells and octants, so rounding moves the result by about
+// one float32 ulp of the stored scales.  The flags are for the report only:
+// clamped = the elongation lies beyond the table's feasible limit, eps_act = a
+// tabulated component at the floor.
+constexpr double kPiD = 3.14159265358979323846;
+
+struct FieldEntry {   // three floats of a field pixel, moved as one access
+    float x, y, z;
+};
+
+__device__ void lut_scales(const Job &J, float s, double rho_d, double th_d, double *a, bool &clamped, bool &eps_act)
+{
+    // table coordinates in binary64: next to the clamped row (u = 0) neighbouring
+    // nodes differ by O(1), so the coordinate must be exact to far below 1e-6
+    constexpr double kQ = 0.25 * kPiD, kInvPi = 1.0 / kPiD, kInvQ = 4.0 / kPiD;
+    const double th = th_d - kPiD * floor(th_d * kInvPi);
+    const int k = min(max((int)floor(th * kInvQ), 0), 3);
+    const double phi_d = th - k * kQ;
+    const int n = J.lut_n;
+    const double fu = div_pos(1.0, rho_d) * (n - 1), fp = phi_d * kInvQ * (n - 1);
+    const int i0 = min(max((int)floor(fu), 0), n - 2), j0 = min(max((int)floor(fp), 0), n - 2);
+    const float wu = (float)(fu - i0), wp = (float)(fp - j0);
+    const float phi = (float)phi_d, rho = (float)rho_d;
+    const float4 *T = reinterpret_cast<const float4 *>(J.lut) + (int64_t)i0 * n + j0;
+    const float4 t00 = T[0], t01 = T[1], t10 = T[n], t11 = T[n + 1];
+    const float w00 = (1.0f - wu) * (1.0f - wp), w01 = (1.0f - wu) * wp, w10 = wu * (1.0f - wp), w11 = wu * wp;
+    float v[4];
+    v[0] = w00 * t00.x + w01 * t01.x + w10 * t10.x + w11 * t11.x;
+    v[1] = w00 * t00.y + w01 * t01.y + w10 * t10.y + w11 * t11.y;
+    v[2] = w00 * t00.z + w01 * t01.z + w10 * t10.z + w11 * t11.z;
+    v[3] = w00 * t00.w + w01 * t01.w + w10 * t10.w + w11 * t11.w;
+    const float r = sqrtf(s);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[(q + k) & 3] = (double)(r * v[q]);
+    // report: the two diagonal-dominance conditions at s = 1 (as rho_limit)
+    float sn, c;
+    sincosf(phi, &sn, &c);
+    const float cs = fabsf(c * sn), e = (float)J.lut_eps / 6.0f;
+    const float k1 = c * c - cs - e, k2 = sn * sn - cs - e;
+    clamped = (k1 < 0.0f && rho * -k1 > sn * sn + cs - e) || (k2 < 0.0f && rho * -k2 > c * c + cs - e);
+    const float vmin = fminf(fminf(v[0], v[1]), fminf(v[2], v[3]));
+    eps_act = vmin * vmin <= (float)J.lut_eps * (1.0f + 1e-5f);
+}
+
+// (s, rho, theta) of a covariance entry; false if it is not positive definite.
+// The smaller eigenvalue as det / larger (no cancellation).
+__device__ bool srt_of_cov(double C11, double C12, double C22, float &s, double &rho, double &th)
+{
+    if (!(isfinite(C11) && isfinite(C12) && isfinite(C22))) return false;
+    const double det = C11 * C22 - C12 * C12;
+    if (!(C11 > 0.0 && C22 > 0.0 && det > 0.0)) return false;
+    const double sd = C11 + C22;
+    const double lmax = 0.5 * (sd + sqrt((C11 - C22) * (C11 - C22) + 4.0 * C12 * C12));
+    s = (float)sd;
+    rho = lmax * lmax / det;   // lmax / lmin with lmin = det / lmax
+    th = 0.5 * atan2(2.0 * C12, C11 - C22);
+    return true;
+}
+
+__global__ void k_lut_build(float4 *T, int n, double eps)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    const int i = idx / n, j = idx - i * n;
+    const double rho = i > 0 ? (double)(n - 1) / (double)i : 1e300;   // i = 0: unbounded (clamped)
+    double a[4];
+    bool cl, ea;
+    solve_srt(sqrt(0.5), rho, (double)j * (0.25 * kPiD) / (double)(n - 1), eps, a, cl, ea);
+    T[idx] = make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]);
+}
+
 __device__ __forceinline__ float wave_max(float v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -225,6 +300,7 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 // One block: 64 columns x (4 waves x kSmapRows) rows, inside one tile.
+template <bool LUT>
 __device__ void scale_map_block(const Job &J, int lb)
 {
     __shared__ float s_rx[4], s_ry[4];
@@ -236,9 +312,21 @@ __device__ void scale_map_block(const Job &J, int lb)
     const int64_t c = (int64_t)bx * kSmapCols + lane;
     float rx = 0.f, ry = 0.f;
     uint32_t ncl = 0, nea = 0, nbad = 0, novf = 0;
-    for (int k = 0; k < kSmapRows; ++k) {
+    // table lookup: the pixels' field entries are loaded up front (one 12-byte
+    // access each), so the four rows' memory latencies overlap
+    FieldEntry pf[kSmapRows];
+    if constexpr (LUT) {
+        if (J.f_kind != kScales4) {
+#pragma unroll
+            for (int k = 0; k < kSmapRows; ++k) {
+                const int64_t r = (int64_t)by * rows_per_block + wave * kSmapRows + k;
+                if (r < J.H && c < J.W) pf[k] = *reinterpret_cast<const FieldEntry *>(J.field + r * J.f_rs + c * 3);
+            }
+        }
+    }
+    auto pixel = [&](int k) {
         const int64_t r = (int64_t)by * rows_per_block + wave * kSmapRows + k;
-        if (!(r < J.H && c < J.W)) continue;
+        if (!(r < J.H && c < J.W)) return;
         double a[4];
         bool cl = false, ea = false, bad = false;
         const float *fv = J.field + r * J.f_rs;
@@ -247,10 +335,23 @@ __device__ void scale_map_block(const Job &J, int lb)
             a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
             bad = !(a[0] > 0.0 && a[1] > 0.0 && a[2] > 0.0 && a[3] > 0.0 && isfinite(a[0] + a[1] + a[2] + a[3]));
         } else {
-            const float f0 = fv[c * 3], f1 = fv[c * 3 + 1], f2 = fv[c * 3 + 2];
+            float f0, f1, f2;
+            if constexpr (LUT) {
+                f0 = pf[k].x; f1 = pf[k].y; f2 = pf[k].z;
+            } else {
+                f0 = fv[c * 3]; f1 = fv[c * 3 + 1]; f2 = fv[c * 3 + 2];
+            }
             if (J.f_kind == kSrt3) {
                 bad = !(isfinite(f0) && isfinite(f1) && isfinite(f2) && f0 > 0.f && f1 >= 1.f);
-                if (!bad) solve_srt(f0, f1, f2, J.eps_full, a, cl, ea);
+                if (!bad) {
+                    if (LUT) lut_scales(J, 2.0f * f0 * f0, (double)f1, (double)f2, a, cl, ea);
+                    else solve_srt(f0, f1, f2, J.eps_full, a, cl, ea);
+                }
+            } else if (LUT) {
+                float s;
+                double rho, th;
+                bad = !srt_of_cov(f0, f1, f2, s, rho, th);
+                if (!bad) lut_scales(J, s, rho, th, a, cl, ea);
             } else {
                 bad = !solve_cov(f0, f1, f2, J.eps_full, a, cl, ea);
             }
@@ -274,6 +375,12 @@ __device__ void scale_map_block(const Job &J, int lb)
         ncl += cl;
         nea += ea;
         nbad += bad;
+    };
+    if constexpr (LUT) {
+#pragma unroll
+        for (int k = 0; k < kSmapRows; ++k) pixel(k);
+    } else {
+        for (int k = 0; k < kSmapRows; ++k) pixel(k);
     }
     // block reduction, then one set of atomics per block on the tile's record
     rx = wave_max(rx);
@@ -309,12 +416,19 @@ __device__ void scale_map_block(const Job &J, int lb)
     __syncthreads();   // the shared records are reused by the next block of a persistent loop
 }
 
-// occupancy 4 (<= 128 VGPRs, a few spilled): measured faster than 3 without spills or 5
+// The solve: occupancy 4 (<= 128 VGPRs, a few spilled), measured faster than 3
+// without spills or 5.  The table lookup is light and keeps the default.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map(Job J)
 {
     // blocks of 16 pixel rows; the launch starts at the first row of tile row tr0
     const int nbx = (int)((J.W + kSmapCols - 1) / kSmapCols);
-    scale_map_block(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
+    scale_map_block<false>(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
+}
+
+__global__ __launch_bounds__(256) void k_scale_map_lut(Job J)
+{
+    const int nbx = (int)((J.W + kSmapCols - 1) / kSmapCols);
+    scale_map_block<true>(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map_batch(const Job *jobs, int n, int total)
@@ -322,7 +436,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
         const Job &J = jobs[j];
-        scale_map_block(J, b - J.smap_base);
+        scale_map_block<false>(J, b - J.smap_base);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scale_map_batch_lut(const Job *jobs, int n, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
+        const Job &J = jobs[j];
+        scale_map_block<true>(J, b - J.smap_base);
     }
 }
 
@@ -1109,7 +1232,15 @@ hipError_t launch_scale_map(const Job &j, hipStream_t s)
     const int64_t r0 = (int64_t)j.tr0 * j.T, r1 = std::min((int64_t)j.tr1 * j.T, j.H);
     if (r1 <= r0) return hipSuccess;
     const int nb = scale_map_blocks(r1 - r0, j.W);
-    hipLaunchKernelGGL(k_scale_map, dim3(nb), dim3(256), 0, s, j);
+    if (j.lut) hipLaunchKernelGGL(k_scale_map_lut, dim3(nb), dim3(256), 0, s, j);
+    else hipLaunchKernelGGL(k_scale_map, dim3(nb), dim3(256), 0, s, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_lut_build(float *lut, int n, double eps, hipStream_t s)
+{
+    const int nn = n * n;
+    hipLaunchKernelGGL(k_lut_build, dim3((nn + 255) / 256), dim3(256), 0, s, reinterpret_cast<float4 *>(lut), n, eps);
     return hipGetLastError();
 }
 
@@ -1182,11 +1313,12 @@ hipError_t launch_fd(const Job &j, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, hipStream_t s)
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s)
 {
     if (total_blocks == 0) return hipSuccess;
     grid = std::max(1, std::min(grid, total_blocks));
-    hipLaunchKernelGGL(k_scale_map_batch, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks);
+    if (lut) hipLaunchKernelGGL(k_scale_map_batch_lut, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks);
+    else hipLaunchKernelGGL(k_scale_map_batch, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks);
     return hipGetLastError();
 }
 

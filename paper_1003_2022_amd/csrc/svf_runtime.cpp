@@ -82,6 +82,13 @@ svf_status check_opts(svf_ctx *ctx, const svf_opts *o, int T)
         return fail(ctx, SVF_EINVAL, "opts.bands must be in [0, %d]", svf_ctx::kMaxBands);
     if (o->boundary < SVF_BOUNDARY_ZERO || o->boundary > SVF_BOUNDARY_SYMMETRIC)
         return fail(ctx, SVF_EINVAL, "opts.boundary must be 0..2");
+    if (o->scale_map != SVF_SCALE_SOLVE && o->scale_map != SVF_SCALE_LUT)
+        return fail(ctx, SVF_EINVAL, "opts.scale_map must be 0 or 1");
+    if (o->scale_map == SVF_SCALE_LUT) {
+        if (o->lut_nodes < 9 || o->lut_nodes > 1025) return fail(ctx, SVF_EINVAL, "opts.lut_nodes must be in [9, 1025]");
+        if (!(o->lut_eps_rel > 0.0 && o->lut_eps_rel <= 1.0))
+            return fail(ctx, SVF_EINVAL, "opts.lut_eps_rel must be in (0, 1]");
+    }
     return SVF_OK;
 }
 
@@ -250,6 +257,38 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
     return j;
 }
 
+svf_status attach_lut(svf_ctx *ctx, const svf_opts &o, Job &j, hipStream_t stream)
+{
+    j.lut = nullptr;
+    j.lut_n = 0;
+    j.lut_eps = 0.0;
+    if (o.scale_map != SVF_SCALE_LUT) return SVF_OK;
+    if (!ctx->lut || ctx->lut_n != o.lut_nodes || ctx->lut_eps != o.lut_eps_rel) {
+        hipError_t e;
+        if (ctx->lut) {   // kernels of earlier calls may still read the old table
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+            hipFree(ctx->lut);
+            ctx->lut = nullptr;
+            ctx->lut_n = 0;
+        }
+        const size_t bytes = (size_t)o.lut_nodes * o.lut_nodes * 4 * sizeof(float);
+        e = hipMalloc(reinterpret_cast<void **>(&ctx->lut), bytes);
+        if (e != hipSuccess) {
+            ctx->lut = nullptr;
+            return fail(ctx, SVF_ENOMEM, "scale table hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        e = launch_lut_build(ctx->lut, o.lut_nodes, o.lut_eps_rel, stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "scale table launch");
+        ctx->lut_n = o.lut_nodes;
+        ctx->lut_eps = o.lut_eps_rel;
+    }
+    j.lut = ctx->lut;
+    j.lut_n = ctx->lut_n;
+    j.lut_eps = ctx->lut_eps;
+    return SVF_OK;
+}
+
 }  // namespace svf
 
 // ============================================================================
@@ -284,6 +323,9 @@ void svf_default_opts(svf_opts *o)
     o->tile = 0;
     o->max_reach_px = kDefaultCap;
     o->boundary = SVF_BOUNDARY_ZERO;
+    o->scale_map = SVF_SCALE_SOLVE;
+    o->lut_nodes = 129;
+    o->lut_eps_rel = 0.125;
 }
 
 svf_status svf_create(svf_ctx **out, int device, size_t hbm_budget_bytes)
@@ -321,6 +363,7 @@ svf_status svf_destroy(svf_ctx *ctx)
     for (auto s : ctx->band_stream)
         if (s) hipStreamDestroy(s);
     if (ctx->ws) hipFree(ctx->ws);
+    if (ctx->lut) hipFree(ctx->lut);
     if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
     delete ctx;
     return SVF_OK;
@@ -374,6 +417,8 @@ svf_status svf_scale_map(svf_ctx *ctx, const svf_field *field, int64_t H, int64_
     Job j = base_job(&im, field, order, &o, p, ws);
     j.scales = scales_out;
     j.sc_rs = W * 4;
+    st = attach_lut(ctx, o, j, stream);
+    if (st) return st;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(p.off_scales / 4), stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "fill");
     e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(j, stream); });
@@ -451,6 +496,8 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
     hipSetDevice(ctx->device);
     unsigned char *ws = static_cast<unsigned char *>(ctx->ws) + ws_off;
     Job j = base_job(in, field, order, &o, p, ws);
+    st = attach_lut(ctx, o, j, stream);
+    if (st) return st;
     j.out = static_cast<float *>(out->data);
     j.out_rs = out->row_stride;
 

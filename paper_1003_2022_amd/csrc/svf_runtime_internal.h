@@ -38,6 +38,10 @@ struct svf_ctx {
     hipStream_t band_stream[kMaxBands] = {};
     std::vector<hipEvent_t> band_events;   // [0]: fork; then pass * kMaxBands + band
     hipEvent_t take_event();
+    // look-up-table scale map: the table of the last (nodes, floor) asked for
+    float *lut = nullptr;
+    int lut_n = 0;
+    double lut_eps = 0.0;
 };
 
 namespace svf {
@@ -61,6 +65,8 @@ svf_status ensure_pinned(svf_ctx *ctx, size_t bytes);
 void fill_report(const TileStat *ts, size_t nt, int order, svf_report *rep);
 Job base_job(const svf_image *in, const svf_field *field, int order, const svf_opts *o, const Plan &p,
              unsigned char *ws);
+// SVF_SCALE_LUT: build (or reuse) the context's table on `stream` and point j at it
+svf_status attach_lut(svf_ctx *ctx, const svf_opts &o, Job &j, hipStream_t stream);
 svf_status run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
                       svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off);
 

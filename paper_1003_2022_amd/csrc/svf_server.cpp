@@ -127,6 +127,7 @@ struct Server {
     svf_server_stats_t stats{};
     double busy_since = -1;
     std::string err;
+    float *lut = nullptr;              // the server's own scale table (SVF_SCALE_LUT)
 };
 
 Server *srv(svf_ctx *ctx) { return static_cast<Server *>(ctx->server); }
@@ -143,7 +144,7 @@ bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *coun
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(j.tstat), 0u,
                             (int64_t)j.ntr * j.ntc * (int64_t)(sizeof(TileStat) / 4), S->stream);
     }
-    if (e == hipSuccess && nsmap) e = launch_scale_map_batch(b.d, nsmap, tot_smap, kPersistentScale, S->stream);
+    if (e == hipSuccess && nsmap) e = launch_scale_map_batch(b.d, nsmap, tot_smap, kPersistentScale, S->lut != nullptr, S->stream);
     for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
         if (counts[ch]) e = launch_preint_batch(b.d + ch * S->cap, counts[ch], tot_tiles[ch], kPersistentPreint,
                                                 S->cfg.opts.preint, kc, S->stream);
@@ -241,6 +242,11 @@ void loop(Server *S)
             pp.off_g = q.off + p.off_g;
             kc = std::max(kc, batch_chunks_for(p.T, p.cap));
             Job base = base_job(&q.r.in, &q.r.field, q.r.order, &S->cfg.opts, pp, S->arena_base);
+            if (S->lut) {
+                base.lut = S->lut;
+                base.lut_n = S->cfg.opts.lut_nodes;
+                base.lut_eps = S->cfg.opts.lut_eps_rel;
+            }
             base.out = static_cast<float *>(q.r.out.data);
             base.out_rs = q.r.out.row_stride;
             if (q.pass == 0) {
@@ -306,6 +312,10 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
     S->step_px = (int64_t)(c.step_mpixels > 0 ? c.step_mpixels : 64) * 1000000;
     hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&S->arena_base, c.hbm_budget_bytes);
+    if (e == hipSuccess && c.opts.scale_map == SVF_SCALE_LUT) {
+        e = hipMalloc(reinterpret_cast<void **>(&S->lut), (size_t)c.opts.lut_nodes * c.opts.lut_nodes * 16);
+        if (e == hipSuccess) e = launch_lut_build(S->lut, c.opts.lut_nodes, c.opts.lut_eps_rel, S->stream);
+    }
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipMalloc(&S->buf[i].d, sizeof(Job) * kTables * S->cap);
         if (e == hipSuccess) e = hipHostMalloc(&S->buf[i].h, sizeof(Job) * kTables * S->cap, hipHostMallocDefault);
@@ -318,6 +328,7 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
             if (b.ev) hipEventDestroy(b.ev);
         }
         if (S->arena_base) hipFree(S->arena_base);
+        if (S->lut) hipFree(S->lut);
         if (S->stream) hipStreamDestroy(S->stream);
         delete S;
         return fail(ctx, SVF_ENOMEM, "server allocation: %s", hipGetErrorString(e));
@@ -434,6 +445,7 @@ svf_status svf_server_stop(svf_ctx *ctx)
         hipEventDestroy(b.ev);
     }
     hipFree(S->arena_base);
+    if (S->lut) hipFree(S->lut);
     hipStreamDestroy(S->stream);
     delete S;
     ctx->server = nullptr;

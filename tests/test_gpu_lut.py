@@ -1,0 +1,156 @@
+"""GPU parity of the look-up-table scale map (Sec. 3.2.2, O1/O2) against the
+CPU oracle's table: the scales of svf_scale_map (float32 stores of the same
+interpolation: relative 1e-6), and the filter driven by them (the filter's bar,
+1e-5 per pixel); batched and served launches with the table agree with
+svf_filter; the table is rebuilt when its parameters change.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1003_2022_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1003_2022_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def random_srt(n, seed):
+    rng = np.random.default_rng(seed)
+    sig = 0.5 + 30 * rng.random(n) ** 2
+    rho = 1 + 60 * rng.random(n) ** 3          # many beyond the feasible limit (clamped rows of the table)
+    th = math.pi * rng.random(n)
+    th[:8] = [0.0, math.pi / 4, math.pi / 2, 3 * math.pi / 4, 1e-7, math.pi / 4 - 1e-7, 0.5, 2.9]
+    rho[:4] = 1.0
+    return np.stack([sig, rho, th], -1).astype(np.float32)
+
+
+def cov_of_srt(f):
+    f = f.astype(np.float64)
+    s = 2 * f[..., 0] ** 2
+    lmax, lmin = s * f[..., 1] / (1 + f[..., 1]), s / (1 + f[..., 1])
+    c, sn = np.cos(f[..., 2]), np.sin(f[..., 2])
+    return np.stack([lmax * c * c + lmin * sn * sn, (lmax - lmin) * c * sn, lmin * c * c + lmax * sn * sn],
+                    -1).astype(np.float32)
+
+
+@pytest.mark.parametrize("nodes,eps_rel", [(129, 0.125), (17, 0.02), (1025, 0.5)])
+@pytest.mark.parametrize("kind", [P.SVF_FIELD_SRT3, P.SVF_FIELD_COV3])
+def test_scale_map_matches_oracle(ctx, nodes, eps_rel, kind):
+    H, W = 64, 80
+    f = random_srt(H * W, 7100 + nodes).reshape(H, W, 3)
+    if kind == P.SVF_FIELD_COV3:
+        f = cov_of_srt(f)
+    o = P.default_opts(scale_map=P.SVF_SCALE_LUT, lut_nodes=nodes, lut_eps_rel=eps_rel)
+    for order in (1, 2):
+        sc = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device=DEV)
+        P.svf_scale_map(ctx, P.field_of(to_dev(f), kind), H, W, order, o, sc)
+        torch.cuda.synchronize()
+        got = sc.cpu().numpy().astype(np.float64)
+        ref = oracle.scales_lut(f, kind, order, nodes, eps_rel) * math.sqrt(order)
+        e = np.abs(got - ref) / ref
+        print(f"nodes {nodes} eps {eps_rel} kind {kind} order {order}: max rel {e.max():.2e}", flush=True)
+        assert np.isfinite(got).all() and e.max() <= 1e-6
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_filter_with_table_matches_oracle(ctx, order):
+    H, W = 120, 150
+    img = I.uniform_image(H, W, 7200 + order)
+    fld = I.srt_field(H, W, 7200 + order, (1.0, 10.0), (1.0, 8.0), corr_len=30.0)
+    out, st, _ = P.filter_tensor(ctx, to_dev(img), to_dev(fld), P.SVF_FIELD_SRT3, order=order, report=True,
+                                 scale_map=P.SVF_SCALE_LUT, tile=64)
+    torch.cuda.synchronize()
+    assert st == P.SVF_OK, ctx.last_error()
+    ref = oracle.filter_lut(img, fld, oracle.FIELD_SRT3, order)
+    got = out.cpu().numpy()
+    scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    e = np.abs(got - ref) / scale
+    print(f"order {order}: max rel {e.max():.2e} rms {np.sqrt(np.mean(e ** 2)):.2e}", flush=True)
+    assert e.max() <= 1e-5 and np.sqrt(np.mean(e ** 2)) <= 1e-6
+
+
+def test_table_rebuilt_on_new_parameters(ctx):
+    H, W = 16, 16
+    f = random_srt(H * W, 7300).reshape(H, W, 3)
+    tf = to_dev(f)
+    for nodes, eps_rel in [(17, 0.125), (129, 0.125), (17, 0.05), (17, 0.125)]:
+        sc = torch.empty((H, W, 4), dtype=torch.float32, device=DEV)
+        P.svf_scale_map(ctx, P.field_of(tf, P.SVF_FIELD_SRT3), H, W, 1,
+                        P.default_opts(scale_map=P.SVF_SCALE_LUT, lut_nodes=nodes, lut_eps_rel=eps_rel), sc)
+        torch.cuda.synchronize()
+        ref = oracle.scales_lut(f, oracle.FIELD_SRT3, 1, nodes, eps_rel)
+        assert np.max(np.abs(sc.cpu().numpy() - ref) / ref) <= 1e-6
+
+
+def test_batch_and_server_with_table(ctx):
+    shapes = [(97, 130, 1, 2), (40, 33, 3, 1), (150, 90, 1, 3)]
+    cases = []
+    for i, (H, W, ch, order) in enumerate(shapes):
+        img = I.uniform_image(H, W, 7400 + i, channels=ch)
+        fld = I.srt_field(H, W, 7400 + i, (1.0, 8.0), (1.0, 6.0), corr_len=20.0)
+        cases.append((to_dev(img), to_dev(fld), order))
+    o = P.default_opts(tile=256, scale_map=P.SVF_SCALE_LUT)
+    singles = []
+    for ti, tf, order in cases:
+        out = torch.empty(ti.shape, dtype=torch.float32, device=DEV)
+        P.svf_filter(ctx, P.image_of(ti), P.field_of(tf, P.SVF_FIELD_SRT3), 4, order, o, P.image_of(out))
+        torch.cuda.synchronize()
+        singles.append(out.cpu().numpy())
+    outs = [torch.zeros(c[0].shape, dtype=torch.float32, device=DEV) for c in cases]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        P.svf_filter_batch(ctx, [P.image_of(c[0]) for c in cases], [P.field_of(c[1], P.SVF_FIELD_SRT3) for c in cases],
+                           [c[2] for c in cases], o, [P.image_of(t) for t in outs], stream, True)
+    stream.synchronize()
+    for i in range(len(cases)):
+        got = outs[i].cpu().numpy()
+        e = np.abs(got - singles[i]) / np.maximum(np.abs(singles[i]), 1e-3 * np.abs(singles[i]).max())
+        assert e.max() <= 1e-6
+    cfg = P.svf_server_cfg()
+    cfg.max_inflight = 4
+    cfg.queue_capacity = 16
+    cfg.hbm_budget_bytes = 1 << 30
+    cfg.opts = P.default_opts(scale_map=P.SVF_SCALE_LUT)
+    P.svf_server_start(ctx, cfg)
+    try:
+        souts = [torch.zeros(c[0].shape, dtype=torch.float32, device=DEV) for c in cases]
+        ids = [P.svf_server_submit(ctx, P.server_request(c[0], c[1], P.SVF_FIELD_SRT3, c[2], souts[i]))
+               for i, c in enumerate(cases)]
+        for rid in ids:
+            res = P.svf_server_wait(ctx, rid, 120.0)
+            assert res.done and res.status == P.SVF_OK
+    finally:
+        P.lib().svf_server_stop(ctx.ptr)
+    for i in range(len(cases)):
+        assert np.array_equal(souts[i].cpu().numpy(), outs[i].cpu().numpy()), f"server request {i}"
+
+
+def test_table_options_rejected(ctx):
+    img = to_dev(I.uniform_image(16, 16, 1))
+    fld = to_dev(I.srt_field(16, 16, 1))
+    out = torch.empty_like(img)
+    for kw in [dict(scale_map=2), dict(scale_map=1, lut_nodes=8), dict(scale_map=1, lut_eps_rel=0.0),
+               dict(scale_map=1, lut_eps_rel=1.5)]:
+        with pytest.raises(P.SvfError) as ei:
+            P.svf_filter(ctx, P.image_of(img), P.field_of(fld, P.SVF_FIELD_SRT3), 4, 1, P.default_opts(**kw),
+                         P.image_of(out))
+        assert ei.value.status == P.SVF_EINVAL
