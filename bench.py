@@ -64,7 +64,8 @@ SEED = 3000
 # algorithmic work per output pixel and pass (derivations in the design doc)
 FD_FLOPS_PER_PX = 640          # FP64 flops (FMA = 2) of the 16-tap difference with 7-point ZP interpolation
 ALGO_BYTES_PER_PX_PASS = 36    # f 4 + field 12 + g write 8 + g read 8 + out 4
-KERNEL_SRC = ROOT / "paper_1003_2022_amd" / "csrc" / "svf_kernels.hip"
+# sources of the finite-difference kernel: its file and the device helpers it includes
+KERNEL_SRCS = [ROOT / "paper_1003_2022_amd" / "csrc" / "svf_fd.hip", ROOT / "paper_1003_2022_amd" / "csrc" / "svf_device.h"]
 TRAFFIC_SUMMARY = ROOT / "profiles" / "k_fd_4096sq_order2_hbm_traffic.txt"
 
 
@@ -73,7 +74,7 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(KERNEL_SRC.read_bytes()).hexdigest()[:16]
+    return hashlib.sha256(b"".join(f.read_bytes() for f in KERNEL_SRCS)).hexdigest()[:16]
 
 
 def fd_traffic_per_launch():

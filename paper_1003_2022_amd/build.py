@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libsvf.so"
-SOURCES = ["svf_kernels.hip", "svf_st.hip", "svf_runtime.cpp", "svf_batch.cpp", "svf_server.cpp", "svf_st.cpp"]
+SOURCES = ["svf_kernels.hip", "svf_fd.hip", "svf_st.hip", "svf_runtime.cpp", "svf_batch.cpp", "svf_server.cpp", "svf_st.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
