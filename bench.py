@@ -32,10 +32,15 @@ Beside it, in the same JSON line:
                 the (s, rho, theta) field by the eigenvalue rules, then the
                 order-2 filter, mirror boundary; ms per step and per-kernel
                 times (its parity with the oracle at this size is a test);
+  table2        the analogue of the paper's Table 2: constant isotropic filters
+                sigma in {1, 2, 4, 8, 16, 32} px, order 1, on 512^2 and 4096^2
+                FP32 images: time per filter (and, at 512^2, the latency of one
+                synchronous call), beside the paper's ~100 ms per 512^2 filter
+                (Java, 2.66 GHz CPU);
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve] [--no-precision]
-                    [--no-smooth] [--no-lut]
+                    [--no-smooth] [--no-lut] [--no-table2]
                     [--calib-copy] [--preint f64|f32c] [--tile T] [--qps Q] [--serve-seconds S]
 """
 from __future__ import annotations
@@ -303,6 +308,45 @@ def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, step_mpx=0, n_sat=120):
     return out
 
 
+# ----------------------------------------------------------------------------- Table 2 leg
+
+def table2_leg(P, I, ctx, torch, steps=20):
+    """Constant isotropic filters of several sizes, order 1 (the paper's Table 2 at 512^2, and 4096^2)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {"workload": "FP32 uniform image, constant isotropic SRT3 field (sigma, 1, 0), order 1, default options; "
+                       "paper (Table 2): 100-103 ms per 512x512 filter for sizes s = 1..16 (Java, 2.66 GHz Intel)",
+           "rows": []}
+    for n in (512, 4096):
+        ti = torch.from_numpy(I.uniform_image(n, n, SEED + 5)).to(dev)
+        out = torch.empty_like(ti)
+        for sigma in (1.0, 2.0, 4.0, 8.0, 16.0, 32.0):
+            tf = torch.from_numpy(I.constant_srt_field(n, n, sigma)).to(dev)
+            im_d, fl_d, o_d = P.image_of(ti), P.field_of(tf, P.SVF_FIELD_SRT3), P.image_of(out)
+            o = P.default_opts()
+            P.svf_filter(ctx, im_d, fl_d, 4, 1, o, o_d, stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                P.svf_filter(ctx, im_d, fl_d, 4, 1, o, o_d, stream)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / steps
+            row = {"image": n, "sigma": sigma, "s_px2": 2 * sigma * sigma, "ms_per_filter": round(ms, 4),
+                   "Mpixel_s": round(n * n / (ms * 1e-3) / 1e6, 1)}
+            if n == 512:   # one call from the host to the finished result
+                lat = []
+                for _ in range(10):
+                    t = time.perf_counter()
+                    P.svf_filter(ctx, im_d, fl_d, 4, 1, o, o_d, stream)
+                    torch.cuda.synchronize()
+                    lat.append((time.perf_counter() - t) * 1e3)
+                row["sync_call_ms_median"] = round(float(np.median(lat)), 4)
+            res["rows"].append(row)
+            log(f"table2 {n}^2 sigma {sigma}: {ms:.3f} ms/filter ({row['Mpixel_s']} Mpx/s)"
+                + (f", synchronous call {row['sync_call_ms_median']:.3f} ms" if n == 512 else ""))
+    return res
+
+
 # ----------------------------------------------------------------------------- smoothing leg
 
 ST_SIGMA_W, ST_GAIN = 2.0, 120.0
@@ -474,6 +518,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-variant leg")
     ap.add_argument("--no-smooth", action="store_true", help="skip the feature-preserving smoothing leg")
     ap.add_argument("--no-lut", action="store_true", help="skip the look-up-table scale-map leg")
+    ap.add_argument("--no-table2", action="store_true", help="skip the Table 2 (constant-size sweep) leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
@@ -605,6 +650,8 @@ def main():
     }
     if not args.no_precision:
         line["precision"] = precision_leg(P, I, ctx, img, fld, ti, tf, torch)
+    if not args.no_table2:
+        line["table2"] = table2_leg(P, I, ctx, torch)
     if not args.no_lut:
         line["scale_lut"] = lut_leg(P, ctx, ti, tf, fld, torch)
     if not args.no_smooth:

@@ -52,7 +52,13 @@ constexpr int kRegS = kFdSide + 2 * kRegM + 3;           // 27: region side
 constexpr int kRegN = kRegS * kRegS;                     // 729 samples
 constexpr int kRegLoads = (kRegN + 255) / 256;           // 3 per thread
 constexpr int kRegPad = kRegLoads * 256;                 // 768: LDS stride of a region (branch-free staging)
-constexpr int kFdPrefetch = 3;                           // taps whose loads are in flight
+constexpr int kFdPrefetch = 3;                           // taps whose loads are in flight (one channel)
+// Several channels: one tap ahead.  The staging registers of three taps ahead
+// cost 3-channel blocks an occupancy step (143 -> 110 VGPRs with one tap);
+// measured at 4096^2, 3 channels: 1658 -> 1510 us per pass (two taps: 1521).
+constexpr int kFdPrefetchMulti = 1;
+template <int NCH>
+constexpr int fd_prefetch() { return NCH == 1 ? kFdPrefetch : kFdPrefetchMulti; }
 
 template <int PRE>
 __device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
@@ -248,8 +254,8 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         rs[ch] = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<unsigned char *>(gbase + ((int64_t)tile * J.C + ch) * J.slot_elems * 8), 0, slot_bytes,
             kBufWord3);
-    // loads of tap j go to register slot j % kFdPrefetch; tap j is fetched kFdPrefetch
-    // taps before it is staged
+    // loads of tap j go to register slot j % PF; tap j is fetched PF taps before it
+    // is staged
     // Region entry e = t + 256 k of tap i is window sample (AY + e / 27) * ww + AX + e % 27:
     // a fixed per-thread part and a uniform per-tap part.  Entries past kRegN are
     // loaded and staged but never read.
@@ -259,7 +265,8 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         const int e = t + 256 * k;
         toff[k] = (e / kRegS) * ww + e % kRegS;
     }
-    double pre[kFdPrefetch][NCH][kRegLoads];
+    constexpr int PF = fd_prefetch<NCH>();
+    double pre[PF][NCH][kRegLoads];
     auto fetch = [&](int i) {   // region of the tap processed at step i
         const int xi = step_q1(i) + 2 * step_q2(i) + 4 * step_q4(i);
         const int yi = step_q2(i) + 2 * step_q3(i) + 4 * step_q4(i);
@@ -268,14 +275,14 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         for (int k = 0; k < kRegLoads; ++k) {
             const uint32_t off = (uint32_t)(sb + toff[k]) * 8u;   // negative wraps: OOB -> 0
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) pre[i % kFdPrefetch][ch][k] = gload<PRE>(rs[ch], off);
+            for (int ch = 0; ch < NCH; ++ch) pre[i % PF][ch][k] = gload<PRE>(rs[ch], off);
         }
     };
     auto stage = [&](int i) {
 #pragma unroll
         for (int k = 0; k < kRegLoads; ++k) {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) lds[i & 1][ch][t + 256 * k] = pre[i % kFdPrefetch][ch][k];
+            for (int ch = 0; ch < NCH; ++ch) lds[i & 1][ch][t + 256 * k] = pre[i % PF][ch][k];
         }
     };
     R acc[NCH];
@@ -283,14 +290,14 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
     for (int ch = 0; ch < NCH; ++ch) acc[ch] = (R)0;
     bool outside = false;   // some stencil of this lane left its staged region
 #pragma unroll
-    for (int j = 0; j < kFdPrefetch; ++j) fetch(j);
+    for (int j = 0; j < PF; ++j) fetch(j);
     stage(0);
     lds_barrier();
     R gdx[2], gdy[2];   // remainders of the current group's abscissae / ordinates
     int glx[2], gly[2];  // their region offsets (gly in samples of whole rows)
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        if (i + kFdPrefetch < 16) fetch(i + kFdPrefetch);
+        if (i + PF < 16) fetch(i + PF);
         const int q1 = step_q1(i), q2 = step_q2(i), q3 = step_q3(i), q4 = step_q4(i);
         if ((i & 3) == 0) {
 #pragma unroll
