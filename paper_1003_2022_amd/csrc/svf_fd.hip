@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "svf_device.h"
@@ -359,6 +360,133 @@ __global__ __launch_bounds__(256) void k_fd_batch(const Job *jobs, int n, int to
     fd_block<PRE, NCH, R>(J, b - J.blk_base, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Finite difference of a spatially constant filter (the window of the structure
+// tensor).  Every pixel's taps then sit at the same offsets with the same
+// remainders, so the 16 x 7 (offset, weight) products of eq. (final_eqn) with
+// the ZP stencils (signs and 1 / (8 a1 a2 a3 a4) folded in) are formed once per
+// block, and one staged region holds every sample of the block's pixels: per
+// pixel and channel, 112 LDS reads and fused multiply-adds.
+// ---------------------------------------------------------------------------
+constexpr int kUniMaxSide = 48;   // largest region side (LDS: side^2 x 8 B per channel)
+
+// Tap i of a constant filter (q1 = bit 0, q2 = bit 1, q3 = bit 2, q4 = bit 3 of i):
+// its position relative to the pixel, nearest lattice point and remainder; every
+// lane computes the same values.
+__device__ __forceinline__ void uni_tap(int i, double a1, double ap2, double a3, double ap4, int &ox, int &oy,
+                                        double &dx, double &dy)
+{
+    const int q1 = i & 1, q2 = (i >> 1) & 1, q3 = (i >> 2) & 1, q4 = (i >> 3) & 1;
+    double x = 0.5 * (a1 + ap2 - ap4 - 1.0), y = 0.5 * (ap2 + a3 + ap4 - 3.0);
+    if (q1) x -= a1;
+    if (q2) { x -= ap2; y -= ap2; }
+    if (q3) y -= a3;
+    if (q4) { x += ap4; y -= ap4; }
+    const double rx = rint(x), ry = rint(y);
+    ox = (int)rx;
+    oy = (int)ry;
+    dx = x - rx;
+    dy = y - ry;
+}
+
+// LDS: the weight table, then NCH regions of `cap` samples (dynamic: sized by the
+// launch for the filter at hand, so that small regions let more blocks share a CU)
+template <int PRE, int NCH>
+__global__ __launch_bounds__(256) void k_fd_uniform(Job J, int nblocks, int cap)
+{
+    extern __shared__ double dyn[];
+    double *tab = dyn;             // 16 x 7 weights (signs and 1 / (8 a1 a2 a3 a4) folded in)
+    double *lds = dyn + 112;       // NCH regions of cap samples
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (lb >= nblocks) return;
+    const int bpt_x = J.T / kFdSide, bpt = bpt_x * bpt_x;
+    const int gb = J.tr0 * J.ntc * bpt + lb;
+    const int tile = gb / bpt, rem = gb - tile * bpt;
+    if (tile >= J.ntr * J.ntc) return;   // uniform
+    const int by = rem / bpt_x, bx = rem - by * bpt_x;
+    const int ti = tile / J.ntc, tj = tile - ti * J.ntc;
+    const int64_t br0 = (int64_t)ti * J.T + by * kFdSide, bc0 = (int64_t)tj * J.T + bx * kFdSide;
+    if (br0 >= J.H || bc0 >= J.W) return;   // uniform
+    const int t = threadIdx.x;
+    const Window w = window_of(J, tile);
+    const float4 af = *reinterpret_cast<const float4 *>(J.scales + br0 * J.sc_rs + bc0 * 4);   // any pixel
+    const double m = J.inv_sqrt_m_d;
+    const double a1 = (double)af.x * m, a2 = (double)af.y * m, a3 = (double)af.z * m, a4 = (double)af.w * m;
+    const double ap2 = a2 * kRsqrt2, ap4 = a4 * kRsqrt2;
+    int oxmin = 1 << 20, oxmax = -(1 << 20), oymin = 1 << 20, oymax = -(1 << 20);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int ox, oy;
+        double dx, dy;
+        uni_tap(i, a1, ap2, a3, ap4, ox, oy, dx, dy);
+        oxmin = min(oxmin, ox); oxmax = max(oxmax, ox);
+        oymin = min(oymin, oy); oymax = max(oymax, oy);
+    }
+    const int sx = kFdSide + oxmax - oxmin + 2, sy = kFdSide + oymax - oymin + 2;   // region sides
+    if (sx > kUniMaxSide || sy > kUniMaxSide || sx * sy > cap) {   // checked on the host; never stage past LDS
+        const int64_t r = br0 + t / kFdSide, c = bc0 + t % kFdSide;
+        if (r < J.H && c < J.W)
+            for (int ch = 0; ch < NCH; ++ch) J.out[r * J.out_rs + c * J.C + ch] = __builtin_nanf("");
+        return;
+    }
+    if (t < 16) {   // the weights of tap t's 7 stencil samples
+        int ox, oy;
+        double dx, dy;
+        uni_tap(t, a1, ap2, a3, ap4, ox, oy, dx, dy);
+        const ZpTap<double> z(dx, dy);
+        const int q = (t & 1) + ((t >> 1) & 1) + ((t >> 2) & 1) + ((t >> 3) & 1);
+        const double k = ((q & 1) ? -1.0 : 1.0) / (8.0 * a1 * a2 * a3 * a4);   // w_i = (-1)^(q1+..+q4) w
+        double *e = tab + 7 * t;
+        e[0] = k * z.w00; e[1] = k * z.w10; e[2] = k * z.wm0; e[3] = k * z.w01;
+        e[4] = k * z.w0m; e[5] = k * z.w11; e[6] = k * z.w1m;
+    }
+    // stage the region: window rows / columns from the block's corner + (oymin - 1, oxmin - 1)
+    const int wr0 = (int)(br0 - w.r0) + oymin - 1, wc0 = (int)(bc0 - w.c0) + oxmin - 1;
+    const unsigned char *gbase = static_cast<const unsigned char *>(J.g);
+    const int slot_bytes = (int)(J.slot_elems * 8);
+    const int n = sx * sy;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char *>(gbase + ((int64_t)tile * J.C + ch) * J.slot_elems * 8), 0, slot_bytes,
+            kBufWord3);
+        for (int e = t; e < n; e += 256) {
+            const int yy = e / sx, xx = e - yy * sx;
+            lds[ch * cap + e] = gload<PRE>(rs, (uint32_t)((wr0 + yy) * w.w + wc0 + xx) * 8u);
+        }
+    }
+    __syncthreads();
+    const int ly = t / kFdSide, lx = t - ly * kFdSide;
+    const int64_t r = br0 + ly, c = bc0 + lx;
+    if (r >= J.H || c >= J.W) return;
+    // sample offsets from registers (the tap geometry recomputed per tap, the same
+    // in every lane), weights from the table at fixed LDS addresses
+    const int base = ly * sx + lx;
+    double acc[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int ox, oy;
+        double dx, dy;
+        uni_tap(i, a1, ap2, a3, ap4, ox, oy, dx, dy);
+        const bool hz = fabs(dx) >= fabs(dy);
+        const int sxb = dx >= 0.0 ? 1 : -1, syb = dy >= 0.0 ? sx : -sx;
+        const int oa = hz ? sxb : syb, ob = hz ? syb : sxb;
+        const int o0 = base + (oy - oymin + 1) * sx + (ox - oxmin + 1);
+        const int off[7] = {o0, o0 + oa, o0 - oa, o0 + ob, o0 - ob, o0 + oa + ob, o0 + oa - ob};
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const double wt = tab[7 * i + j];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) acc[ch] = fma(wt, lds[ch * cap + off[j]], acc[ch]);
+        }
+    }
+    float *o = J.out + r * J.out_rs + c * J.C;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) o[ch] = (float)acc[ch];
+}
+
 }  // namespace
 
 int fd_blocks_job(const Job &j)
@@ -374,6 +502,35 @@ static hipError_t launch_fd_pr(const Job &j, int nb, int grid, hipStream_t s)
     case 2: hipLaunchKernelGGL((k_fd<PRE, 2, R>), dim3(grid), dim3(256), 0, s, j, nb); break;
     case 3: hipLaunchKernelGGL((k_fd<PRE, 3, R>), dim3(grid), dim3(256), 0, s, j, nb); break;
     case 4: hipLaunchKernelGGL((k_fd<PRE, 4, R>), dim3(grid), dim3(256), 0, s, j, nb); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+namespace {
+// region sides bound: tap spread + rounding of both extremes + the stencil's sample on each side
+int uni_side(double spread) { return kFdSide + (int)std::ceil(spread) + 1 + 2; }
+}  // namespace
+
+bool fd_uniform_fits(double a1, double a2, double a3, double a4, int channels)
+{
+    if (channels != 3) return false;
+    const double ap2 = a2 * 0.70710678118654752440, ap4 = a4 * 0.70710678118654752440;
+    return uni_side(a1 + ap2 + ap4) <= kUniMaxSide && uni_side(ap2 + a3 + ap4) <= kUniMaxSide;
+}
+
+hipError_t launch_fd_uniform(const Job &j, const double *a, hipStream_t s)
+{
+    const int nb = (j.tr1 - j.tr0) * j.ntc * (j.T / kFdSide) * (j.T / kFdSide);
+    if (nb <= 0) return hipSuccess;
+    const int grid = (nb + 7) / 8 * 8;
+    if (j.C != 3 || j.fd_fp32) return hipErrorInvalidValue;
+    const double ap2 = a[1] * 0.70710678118654752440, ap4 = a[3] * 0.70710678118654752440;
+    const int cap = uni_side(a[0] + ap2 + ap4) * uni_side(ap2 + a[2] + ap4);
+    const size_t bytes = (112 + (size_t)3 * cap) * sizeof(double);
+    switch (j.preint) {
+    case kPreF64: hipLaunchKernelGGL((k_fd_uniform<kPreF64, 3>), dim3(grid), dim3(256), bytes, s, j, nb, cap); break;
+    case kPreF32C: hipLaunchKernelGGL((k_fd_uniform<kPreF32C, 3>), dim3(grid), dim3(256), bytes, s, j, nb, cap); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -122,6 +122,10 @@ hipError_t launch_scale_map(const Job &j, hipStream_t s);
 hipError_t launch_lut_build(float *lut, int n, double eps, hipStream_t s);
 hipError_t launch_preint(const Job &j, hipStream_t s);
 hipError_t launch_fd(const Job &j, hipStream_t s);
+// constant filter (every pixel's scales equal; 3 channels, binary64 difference):
+// whether the staged region of a block fits, and the launch
+bool fd_uniform_fits(double a1, double a2, double a3, double a4, int channels);
+hipError_t launch_fd_uniform(const Job &j, const double *pass_a, hipStream_t s);
 // standalone pre-integration of a caller-given window (svf_preintegrate)
 hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c0, int h, int w, void *g,
                                 hipStream_t s);

@@ -492,7 +492,7 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
 // (callers that keep their own buffers at the front of the workspace grow it to
 // ws_off + plan bytes first).
 svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
-                           svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off)
+                           svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off, const double *uniform_a)
 {
     Plan p = plan_for(in, order, &o);
     svf_status st = ensure_workspace(ctx, ws_off + p.bytes);
@@ -530,6 +530,13 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
     };
 
     const int nb = pick_bands(p, o.bands);
+    // a constant filter: the difference kernel that forms the taps once per block
+    const double im = 1.0 / std::sqrt((double)order);
+    double ua_pass[4] = {0, 0, 0, 0};
+    if (uniform_a)
+        for (int k = 0; k < 4; ++k) ua_pass[k] = uniform_a[k] * im;
+    const bool uniform_fd = uniform_a && !o.fd_fp32 && o.preint != SVF_PRE_I64 &&
+                            fd_uniform_fits(ua_pass[0], ua_pass[1], ua_pass[2], ua_pass[3], in->channels);
     if (nb <= 1) {
         e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(pass_job(0, 0, p.ntr), stream); });
         if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
@@ -537,7 +544,7 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
             const Job jp = pass_job(pass, 0, p.ntr);
             e = timed_launch(ctx, kClsPreint, stream, [&] { return launch_preint(jp, stream); });
             if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
-            e = timed_launch(ctx, kClsFd, stream, [&] { return launch_fd(jp, stream); });
+            e = timed_launch(ctx, kClsFd, stream, [&] { return uniform_fd ? launch_fd_uniform(jp, ua_pass, stream) : launch_fd(jp, stream); });
             if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
         }
     } else {

@@ -68,7 +68,8 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
 // SVF_SCALE_LUT: build (or reuse) the context's table on `stream` and point j at it
 svf_status attach_lut(svf_ctx *ctx, const svf_opts &o, Job &j, hipStream_t stream);
 svf_status run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
-                      svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off);
+                      svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off,
+                      const double *uniform_a = nullptr);   // the field's scales where they are all equal
 
 }  // namespace svf
 

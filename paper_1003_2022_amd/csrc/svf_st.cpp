@@ -105,7 +105,8 @@ svf_status st_run(svf_ctx *ctx, const svf_image *in, const svf_st_params &p, con
     wf.data = row;
     wf.kind = SVF_FIELD_SCALES4;
     wf.row_stride = 0;   // every row reads the same constant row
-    svf_status st = run_filter(ctx, &pim, &wf, p.order_w, window_opts(o), &jim, stream, nullptr, L.front);
+    const double ua[4] = {a, a, a, a};   // the stored (float) scales
+    svf_status st = run_filter(ctx, &pim, &wf, p.order_w, window_opts(o), &jim, stream, nullptr, L.front, ua);
     if (st) return st;
     if (F) {
         e = timed_launch(ctx, kClsSt, stream, [&] {
