@@ -310,6 +310,7 @@ typedef struct {
     int64_t submitted, completed, rejected, steps;
     int64_t pixels;             /* output pixels x channels of completed requests */
     double busy_us;             /* wall time with at least one request in flight */
+    int64_t cancelled;          /* requests ended by svf_server_cancel */
 } svf_server_stats_t;
 
 /* Start the scheduler (allocates hbm_budget_bytes on the context's device). */
@@ -320,6 +321,13 @@ svf_status svf_server_submit(svf_ctx *ctx, const svf_request *req, uint64_t *id)
 svf_status svf_server_poll(svf_ctx *ctx, uint64_t id, svf_result *res);
 /* Wait up to timeout_s seconds (< 0: forever) for a request; SVF_EBUSY on timeout. */
 svf_status svf_server_wait(svf_ctx *ctx, uint64_t id, svf_result *res, double timeout_s);
+/* Cancel a request.  A queued request ends at once; one in flight runs no
+ * further pass and ends when the passes already on the device complete (its
+ * output then holds an unspecified mix of passes).  Either way the request
+ * ends with status SVF_ECANCELLED and SVF_OK is returned.  SVF_EBUSY (nothing
+ * changed) when the request is done or its last pass is already launched: it
+ * completes normally; SVF_EINVAL for an unknown id. */
+svf_status svf_server_cancel(svf_ctx *ctx, uint64_t id);
 svf_status svf_server_stats(svf_ctx *ctx, svf_server_stats_t *stats);
 /* Drain the queue, stop the thread, release the server's memory. */
 svf_status svf_server_stop(svf_ctx *ctx);

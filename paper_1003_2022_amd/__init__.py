@@ -70,7 +70,7 @@ class svf_result(C.Structure):
 
 class svf_server_stats_t(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64), ("steps", C.c_int64),
-                ("pixels", C.c_int64), ("busy_us", C.c_double)]
+                ("pixels", C.c_int64), ("busy_us", C.c_double), ("cancelled", C.c_int64)]
 
 
 _lib = None
@@ -127,6 +127,8 @@ def lib() -> C.CDLL:
         L.svf_server_wait.argtypes = [vp, C.c_uint64, P(svf_result), C.c_double]
         L.svf_server_stats.restype = st
         L.svf_server_stats.argtypes = [vp, P(svf_server_stats_t)]
+        L.svf_server_cancel.restype = st
+        L.svf_server_cancel.argtypes = [vp, C.c_uint64]
         L.svf_server_stop.restype = st
         L.svf_server_stop.argtypes = [vp]
     _lib = L
@@ -352,6 +354,16 @@ def svf_server_wait(ctx: Context, rid: int, timeout_s: float = -1.0) -> svf_resu
     res = svf_result()
     ctx.check(lib().svf_server_wait(ctx.ptr, C.c_uint64(rid), C.byref(res), timeout_s))
     return res
+
+
+def svf_server_cancel(ctx: Context, rid: int) -> bool:
+    """Cancel a request: True if it will end with SVF_ECANCELLED, False if it was
+    already completing (done, or its last pass launched); raises for an unknown id."""
+    st = lib().svf_server_cancel(ctx.ptr, C.c_uint64(rid))
+    if st == SVF_EBUSY:
+        return False
+    ctx.check(st)
+    return True
 
 
 def svf_server_stats(ctx: Context) -> svf_server_stats_t:

@@ -13,7 +13,9 @@
 // A request at pass p in step k is at pass p+1 in step k+1; a request whose last
 // pass ran in step k is completed, and its arena range freed, once the host has
 // seen step k's event.  Steps are pipelined one deep: step k+1 is enqueued before
-// the host waits for step k.
+// the host waits for step k.  A cancelled request leaves the queue at once; one
+// in flight gets no further pass and frees its range once the steps already
+// launched with it have completed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,6 +99,11 @@ struct Req {
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = SVF_EBUSY;
     bool done = false;
+    // cancellation: `pending` counts the launched steps that still hold one of the
+    // request's passes (the region stays allocated until it is 0); once the final
+    // pass is launched the request can no longer be cancelled
+    int pending = 0;
+    bool final_sched = false, cancelled = false;
 };
 
 struct StepBuf {
@@ -155,6 +162,28 @@ bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *coun
     return e == hipSuccess;
 }
 
+// Close the busy interval once nothing is in flight (called under S->mu).
+void note_idle(Server *S, double t)
+{
+    if (S->inflight.empty() && S->busy_since >= 0) {
+        S->stats.busy_us += t - S->busy_since;
+        S->busy_since = -1;
+    }
+}
+
+// End an admitted request that was cancelled and has no step on the device
+// (called under S->mu): its region goes back to the arena.
+void end_cancelled(Server *S, uint64_t id, Req &q, double t)
+{
+    q.done = true;
+    q.status = SVF_ECANCELLED;
+    q.t_done = t;
+    S->arena.release(q.off, q.bytes);
+    S->stats.cancelled++;
+    S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), id));
+    note_idle(S, t);
+}
+
 // Host side of a finished step: complete its finishing requests.
 void retire(Server *S, StepBuf &b)
 {
@@ -172,13 +201,14 @@ void retire(Server *S, StepBuf &b)
         S->stats.pixels += q.r.out.H * q.r.out.W * q.r.out.channels;
         S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), id));
     }
+    for (uint64_t id : b.running) {
+        Req &q = S->reqs[id];
+        if (--q.pending == 0 && q.cancelled && !q.done) end_cancelled(S, id, q, t);
+    }
     b.finishing.clear();
     b.running.clear();
     b.pending = false;
-    if (S->inflight.empty() && S->busy_since >= 0) {
-        S->stats.busy_us += t - S->busy_since;
-        S->busy_since = -1;
-    }
+    note_idle(S, t);
     S->cv_done.notify_all();
     S->cv_work.notify_all();
 }
@@ -209,11 +239,13 @@ void loop(Server *S)
             int64_t used = 0;
             for (uint64_t id : S->inflight) {
                 Req &q = S->reqs[id];
-                if (q.pass >= q.r.order) continue;
+                if (q.cancelled || q.pass >= q.r.order) continue;
                 const int64_t px = q.r.in.H * q.r.in.W * q.r.in.channels;
                 if (!running.empty() && used + px > S->step_px) continue;
                 running.emplace_back(id, &q);
                 used += px;
+                q.pending++;
+                if (q.pass + 1 == q.r.order) q.final_sched = true;
             }
             if (running.empty()) {
                 StepBuf &o = S->buf[(k + 1) & 1];
@@ -413,6 +445,34 @@ svf_status svf_server_wait(svf_ctx *ctx, uint64_t id, svf_result *res, double ti
         return SVF_EBUSY;
     }
     fill_result(S->reqs[id], res);
+    return SVF_OK;
+}
+
+svf_status svf_server_cancel(svf_ctx *ctx, uint64_t id)
+{
+    if (!ctx) return SVF_EINVAL;
+    Server *S = srv(ctx);
+    if (!S) return fail(ctx, SVF_EINVAL, "server not running");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(ctx, SVF_EINVAL, "unknown request id");
+    Req &q = it->second;
+    if (q.done || q.final_sched || q.cancelled)
+        return fail(ctx, SVF_EBUSY, "request %llu is already completing", (unsigned long long)id);
+    const double t = now_us();
+    auto qi = std::find(S->queue.begin(), S->queue.end(), id);
+    if (qi != S->queue.end()) {   // still waiting: never touched the device
+        S->queue.erase(qi);
+        q.done = true;
+        q.status = SVF_ECANCELLED;
+        q.t_done = t;
+        S->stats.cancelled++;
+    } else {                      // in flight: no further pass is launched
+        q.cancelled = true;
+        if (q.pending == 0) end_cancelled(S, id, q, t);
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
     return SVF_OK;
 }
 

@@ -7,9 +7,12 @@
 * the server: every request's output is bitwise identical whether it is served
   alone or in a mix, equals svf_filter with the same options to 1e-6, and
   equals the CPU FP64 oracle to 1e-5 (relative, per pixel);
-* admission: a request larger than the memory budget is rejected at submit.
+* admission: a request larger than the memory budget is rejected at submit;
+* failure handling forced from the host: cancellation of queued and in-flight
+  requests, a full queue, a context workspace budget.
 """
 import ctypes as C
+import time
 
 import numpy as np
 import pytest
@@ -190,3 +193,136 @@ def test_server_rejects_over_budget(ctx, cases):
         assert stats.rejected == 1
     finally:
         P.lib().svf_server_stop(ctx.ptr)
+
+
+# ---- failure handling forced from the host: cancellation, a full queue, a workspace budget
+
+BIG = 4096   # one pass of an order-3 request takes long enough (~2 ms) to catch it in flight
+
+
+@pytest.fixture(scope="module")
+def big():
+    img = I.uniform_image(BIG, BIG, 4100)
+    fld = I.srt_field(BIG, BIG, 4100, (1, 8), (1, 4), corr_len=64.0)
+    return to_dev(img), to_dev(fld)
+
+
+def _one_request_budget(order=3):
+    # the workspace of one request at tile 256: holds one request's windows and
+    # scales but not two
+    img = P.svf_image(None, P.SVF_F32, 1, BIG, BIG, BIG)
+    return P.svf_workspace_bytes(img, 4, order, P.default_opts(tile=256))
+
+
+def _srv_cfg(budget, inflight=1, queue=64):
+    cfg = P.svf_server_cfg()
+    cfg.max_inflight = inflight
+    cfg.queue_capacity = queue
+    cfg.hbm_budget_bytes = budget
+    cfg.step_mpixels = 1   # one pass per step
+    cfg.opts = P.default_opts()
+    return cfg
+
+
+def test_server_cancel(ctx, big):
+    """Six order-3 requests behind one slot and a budget for one: the last four
+    are cancelled while queued (they end at once), the first right after its
+    admission (in flight: no further pass).  Whatever the timing, every request
+    ends: SVF_ECANCELLED where the cancel took, else SVF_OK with svf_filter's
+    result.  A request submitted afterwards still runs, so the cancelled
+    request's memory went back to the arena."""
+    timg, tfld = big
+    ref = single(ctx, timg, tfld, 3, tile=256)
+    P.svf_server_start(ctx, _srv_cfg(_one_request_budget()))
+    try:
+        outs = [torch.zeros(timg.shape, dtype=torch.float32, device=DEV) for _ in range(7)]
+        ids = [P.svf_server_submit(ctx, P.server_request(timg, tfld, P.SVF_FIELD_SRT3, 3, outs[i]))
+               for i in range(6)]
+        took = {i: P.svf_server_cancel(ctx, ids[i]) for i in range(2, 6)}
+        print(f"queued cancels: {took}", flush=True)
+        assert all(took.values()), "a request behind a busy slot and a full arena was not still queued"
+        deadline = time.monotonic() + 30.0
+        while P.svf_server_poll(ctx, ids[0]).t_admit_us == 0:
+            assert time.monotonic() < deadline, "the first request was never admitted"
+        took[0] = P.svf_server_cancel(ctx, ids[0])
+        print(f"in-flight cancel took: {took[0]}", flush=True)
+        assert not P.svf_server_cancel(ctx, ids[2]), "a second cancel must report the request as ending"
+        with pytest.raises(P.SvfError) as ei:
+            P.svf_server_cancel(ctx, 10 ** 9)
+        assert ei.value.status == P.SVF_EINVAL
+        res = {i: P.svf_server_wait(ctx, ids[i], 120.0) for i in range(6)}
+        ids.append(P.svf_server_submit(ctx, P.server_request(timg, tfld, P.SVF_FIELD_SRT3, 3, outs[6])))
+        res[6] = P.svf_server_wait(ctx, ids[6], 120.0)
+        st = P.svf_server_stats(ctx)
+    finally:
+        P.svf_server_stop(ctx)
+    for i in range(7):
+        assert res[i].done
+        if took.get(i, False):
+            assert res[i].status == P.SVF_ECANCELLED, (i, res[i].status)
+            assert res[i].t_done_us >= res[i].t_submit_us
+        else:
+            assert res[i].status == P.SVF_OK, (i, res[i].status)
+            assert rel_err(outs[i].cpu().numpy(), ref) <= 1e-6, f"request {i}"
+    for i in range(2, 6):
+        assert res[i].t_admit_us == 0, "a request cancelled in the queue was admitted"
+        assert np.count_nonzero(outs[i].cpu().numpy()) == 0, "a request cancelled in the queue wrote output"
+    n_took = sum(took.values())
+    assert st.submitted == 7 and st.cancelled == n_took and st.completed == 7 - n_took, \
+        (st.submitted, st.cancelled, st.completed)
+
+
+def test_server_queue_full(ctx, big):
+    """Queue capacity 2 behind one slot: of six requests submitted back to back
+    at most three are taken (one admitted, two waiting); the rest are refused
+    with SVF_EBUSY at submit, counted as rejected, and those taken complete."""
+    timg, tfld = big
+    ref = single(ctx, timg, tfld, 3, tile=256)
+    P.svf_server_start(ctx, _srv_cfg(_one_request_budget(), queue=2))
+    try:
+        outs = [torch.zeros(timg.shape, dtype=torch.float32, device=DEV) for _ in range(6)]
+        taken, refused = [], 0
+        for i in range(6):
+            try:
+                taken.append((i, P.svf_server_submit(ctx, P.server_request(timg, tfld, P.SVF_FIELD_SRT3, 3,
+                                                                              outs[i]))))
+            except P.SvfError as e:
+                assert e.status == P.SVF_EBUSY
+                refused += 1
+        res = [(i, P.svf_server_wait(ctx, rid, 120.0)) for i, rid in taken]
+        st = P.svf_server_stats(ctx)
+    finally:
+        P.svf_server_stop(ctx)
+    print(f"taken {len(taken)}, refused {refused}", flush=True)
+    assert refused >= 3 and st.rejected == refused and st.completed == len(taken)
+    for i, r in res:
+        assert r.status == P.SVF_OK
+        assert rel_err(outs[i].cpu().numpy(), ref) <= 1e-6
+
+
+def test_context_budget():
+    """A context whose HBM budget is one small image's workspace: a larger image
+    is refused with SVF_ENOMEM before anything is allocated or launched, and
+    the context still filters images that fit."""
+    small = I.uniform_image(40, 56, 4200)
+    sfld = I.srt_field(40, 56, 4200, (1, 3), (1, 2), corr_len=8.0)
+    big_img = I.uniform_image(300, 300, 4201)
+    bfld = I.srt_field(300, 300, 4201, (1, 3), (1, 2), corr_len=8.0)
+    o = P.default_opts()
+    need = P.svf_workspace_bytes(P.svf_image(None, P.SVF_F32, 1, 40, 56, 56), 4, 2, o)
+    c = P.Context(0, hbm_budget_bytes=need)
+    try:
+        tb, tbf = to_dev(big_img), to_dev(bfld)
+        out_b = torch.zeros(tb.shape, dtype=torch.float32, device=DEV)
+        with pytest.raises(P.SvfError) as ei:
+            P.svf_filter(c, P.image_of(tb), P.field_of(tbf, P.SVF_FIELD_SRT3), 4, 2, o, P.image_of(out_b))
+        assert ei.value.status == P.SVF_ENOMEM and "budget" in str(ei.value)
+        ts, tsf = to_dev(small), to_dev(sfld)
+        out_s = torch.zeros(ts.shape, dtype=torch.float32, device=DEV)
+        P.svf_filter(c, P.image_of(ts), P.field_of(tsf, P.SVF_FIELD_SRT3), 4, 2, o, P.image_of(out_s))
+        torch.cuda.synchronize()
+    finally:
+        c.close()
+    assert np.count_nonzero(out_b.cpu().numpy()) == 0
+    ref = oracle.filter(small, sfld, oracle.FIELD_SRT3, 2)
+    assert rel_err(out_s.cpu().numpy(), ref) <= 1e-5
