@@ -44,6 +44,13 @@ __device__ __forceinline__ Window window_of(const Job &J, int tile)
     Window w;
     w.c0 = c0 - hx - 3;
     w.w = (int)(c1 - c0) + 2 * hx + 5;
+    // even origin and width (at most T + 2 cap + 6): rows of the window start
+    // 16-byte aligned, and pairs of input columns from even columns are 8-byte aligned
+    if (w.c0 & 1) {
+        w.c0 -= 1;
+        w.w += 1;
+    }
+    w.w += w.w & 1;
     w.r0 = r0 - hy - 4;
     w.h = (int)(r1 - r0) + 2 * hy + 5;
     return w;

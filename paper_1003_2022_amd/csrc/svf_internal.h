@@ -137,7 +137,6 @@ hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, i
                            hipStream_t s);
 
 int64_t slot_elems_for(int T, int cap);
-int chunks_for(int T, int cap);         // 512-column chunks of the widest window (single-image sweep)
 int batch_chunks_for(int T, int cap);   // 256-column chunks of the widest window (batched sweep)
 int scale_map_blocks(int64_t H, int64_t W);
 int fd_blocks_job(const Job &j);   // tile-major FD blocks, ragged edge tiles included

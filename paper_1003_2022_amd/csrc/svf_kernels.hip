@@ -5,7 +5,10 @@
 //   k_scale_map : per pixel, covariance field -> box scales (Sec. 3.2.2) and, per tile,
 //                 the support half-widths that size the pre-integration windows.
 //   k_preint    : running sums RS1..RS4 (Sec. 3.1 step (1), Algorithm 1 step 2) of one
-//                 tile's window, one work-group sweeping the rows top to bottom.
+//                 tile's window, one work-group sweeping the rows top to bottom as a
+//                 pipeline of waves (input loads, RS1, RS2..RS4 and stores).
+//   k_preint_window / k_preint_batch : the same sums for a caller's window and for
+//                 the batched launches.
 //   (k_fd, the finite difference, is in svf_fd.hip)
 //
 // Lattice: x = column, y = row, directions u1 = (1,0), u2 = (1,1)/sqrt2, u3 = (0,1),
@@ -442,6 +445,8 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
 //            (Knuth two-sum, Dekker fast-two-sum, FMA two-product).
 // Wave prefix sums use DPP (row shifts 1, 2, 4, 8 then the row broadcasts 15, 31).
 // ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes of a buffer store
+
 template <int CTRL, int RM>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v)
 {
@@ -464,6 +469,12 @@ struct ArF64 {
     template <int CTRL, int RM>
     __device__ static T dpp(T v) { return __longlong_as_double((long long)dpp64<CTRL, RM>((uint64_t)__double_as_longlong(v))); }
     __device__ static void store(void *g, int64_t i, T v) { static_cast<double *>(g)[i] = v; }
+    __device__ static T mul01(T v, T k) { return v * k; }   // k is 0 or 1
+    __device__ static u32x4 pack2(T a, T b)
+    {
+        const uint64_t x = (uint64_t)__double_as_longlong(a), y = (uint64_t)__double_as_longlong(b);
+        return u32x4{(uint32_t)x, (uint32_t)(x >> 32), (uint32_t)y, (uint32_t)(y >> 32)};
+    }
 };
 
 struct ArI64 {
@@ -475,6 +486,8 @@ struct ArI64 {
     template <int CTRL, int RM>
     __device__ static T dpp(T v) { return dpp64<CTRL, RM>(v); }
     __device__ static void store(void *g, int64_t i, T v) { static_cast<unsigned long long *>(g)[i] = v; }
+    __device__ static T mul01(T v, T k) { return v & (0ull - k); }   // k is 0 or 1
+    __device__ static u32x4 pack2(T a, T b) { return u32x4{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)}; }
 };
 
 struct DF {
@@ -527,6 +540,11 @@ struct ArF32C {
         return {__uint_as_float(dpp32<CTRL, RM>(__float_as_uint(v.hi))), __uint_as_float(dpp32<CTRL, RM>(__float_as_uint(v.lo)))};
     }
     __device__ static void store(void *g, int64_t i, T v) { static_cast<float2 *>(g)[i] = make_float2(v.hi, v.lo); }
+    __device__ static T mul01(T v, T k) { return {v.hi * k.hi, v.lo * k.hi}; }   // k is 0 or 1
+    __device__ static u32x4 pack2(T a, T b)
+    {
+        return u32x4{__float_as_uint(a.hi), __float_as_uint(a.lo), __float_as_uint(b.hi), __float_as_uint(b.lo)};
+    }
 };
 
 // inclusive prefix over the 64 lanes of a wave
@@ -783,15 +801,223 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
     }
 }
 
-template <class A, int IN, int KC>
-__global__ __launch_bounds__(kScanThreads + 64) void k_preint(Job J)
+// Row sweep split over the waves of one work-group per window.  Lane l owns the
+// P adjacent columns l P .. l P + P - 1 (P 64 >= the window width, P even);
+// rows go in blocks of D, through a pipeline with one barrier per block:
+//   loader wave      : input rows of block k into an LDS buffer (its memory queue
+//                      holds loads only, kPreAhead blocks ahead, so it waits
+//                      exactly for the oldest);
+//   kPreProd waves   : RS1 of block k - 1 (the lane's serial prefix, then the
+//                      wave prefix of the lane totals by DPP, added to it; rows
+//                      are independent, each wave takes every kPreProd-th) into
+//                      a second LDS buffer;
+//   consumer wave    : RS2..RS4 of block k - 2, row after row: RS2 and RS4 take
+//                      the previous row's value one column to the left / right
+//                      from the lane's registers or, at its first / last column,
+//                      from the neighbouring lane (wave shift by one lane, DPP);
+//                      RS3 stays in registers; results to the window.
+// Each wave alone would be bound by the latency of its instruction chains or of
+// memory; split this way the window's work runs on four SIMDs at once.
+//
+// The last block runs past the window's last row: its loads read valid rows
+// (mapped into the image) and its stores fall outside the window's buffer
+// range, which the hardware drops, as it drops the stores of lanes' columns
+// beyond the window's width; so the blocks have no branch.  Results are written
+// as pairs of columns (16-byte stores: window widths and origins are even, P is
+// even); where the wave's columns are all inside the image and the image is one
+// f32 channel with an even row stride, inputs are read as pairs (8-byte loads).
+constexpr int kPreProd = 2;                          // RS1 waves per window
+constexpr int kPreAhead = 2;                         // blocks of input rows the loader has in flight
+constexpr int kPreWaves = kPreProd + 2;              // + loader + consumer
+constexpr int kPreLds = 2 * 8 * 8 * 64;              // T elements: 2 buffers x D x P x 64 (max over P)
+
+template <int P>
+constexpr int pre_rows() { return P <= 8 ? 8 : 4; }   // D: rows per block
+
+// Input buffer (floats) after the RS1 buffer: 2 x D x P x 64 values, [d][j][lane].
+template <class A>
+__device__ __forceinline__ float *pre_inbuf(typename A::T *lds) { return reinterpret_cast<float *>(lds + kPreLds); }
+
+template <class A, int IN, int P, bool PAIRS>
+__device__ __forceinline__ void preint_loader(const Job &J, int ch, const Window w, typename A::T *lds)
 {
-    __shared__ ScanLds<A, KC> L;
+    static_assert(P % 2 == 0, "column pairs");
+    static_assert(!PAIRS || IN == kInF32, "pair loads read f32 input");
+    using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
+    constexpr int D = pre_rows<P>();
+    const int lane = threadIdx.x & 63, cb = lane * P;
+    const int bnd = J.boundary;
+    const E *in = static_cast<const E *>(J.in);
+    int32_t coff[P];
+    uint32_t cmask = 0;   // columns inside the window (and, zero rule, inside the image)
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int c = cb + j;
+        const int64_t C = w.c0 + c;
+        coff[j] = (int32_t)(ext_index(C, J.W, bnd) * J.C + ch);
+        if (c < w.w && (bnd != kBoundZero || (C >= 0 && C < J.W))) cmask |= 1u << j;
+    }
+    E ring[kPreAhead][D][P];   // input rows of the next kPreAhead blocks
+    auto issue = [&](int rr, E *dst) {   // rows past the window map to valid rows (values unused)
+        const E *rowp = in + ext_index(w.r0 + rr, J.H, bnd) * J.in_rs;
+        if (PAIRS) {   // (buffer loads: plain vector loads get split back into dwords)
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<E *>(rowp + w.c0), 0, 64 * P * (int)sizeof(E), kBufWord3);
+#pragma unroll
+            for (int j = 0; j < P; j += 2) {
+                const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (cb + j) * 4, 0, 0));
+                dst[j] = v.x;
+                dst[j + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < P; ++j) dst[j] = rowp[coff[j]];
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < kPreAhead; ++u)
+#pragma unroll
+        for (int d = 0; d < D; ++d) issue(u * D + d, ring[u][d]);
+    float *inb = pre_inbuf<A>(lds);
+    const int nblk = (w.h + D - 1) / D;
+    for (int k0 = 0; k0 < nblk + 2; k0 += kPreAhead) {
+#pragma unroll
+        for (int u = 0; u < kPreAhead; ++u) {   // block k comes from ring[k % kPreAhead]
+            const int k = k0 + u;
+            if (k >= nblk + 2) break;   // uniform
+            if (k < nblk) {
+                float *buf = inb + (k & 1) * (D * P * 64);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int64_t R = w.r0 + k * D + d;
+                    const bool rin = bnd != kBoundZero || (R >= 0 && R < J.H);
+#pragma unroll
+                    for (int j = 0; j < P; ++j)
+                        buf[(d * P + j) * 64 + lane] = (rin && ((cmask >> j) & 1u)) ? (float)ring[u][d][j] : 0.f;
+                    issue((k + kPreAhead) * D + d, ring[u][d]);
+                }
+            }
+            lds_barrier();
+        }
+    }
+}
+
+template <class A, int P>
+__device__ __forceinline__ void preint_producer(const Window w, typename A::T *lds, int wave)
+{
+    using T = typename A::T;
+    constexpr int D = pre_rows<P>(), DP = D / kPreProd;   // rows of a block, of them this wave's
+    static_assert(DP * kPreProd == D && 2 * D * P * 64 <= kPreLds, "block rows and LDS buffers");
+    const int lane = threadIdx.x & 63;
+    const float *inb = pre_inbuf<A>(lds);
+    const int nblk = (w.h + D - 1) / D;
+    for (int k = 0; k < nblk + 2; ++k) {
+        if (k >= 1 && k <= nblk) {   // block k - 1
+            const float *src = inb + ((k - 1) & 1) * (D * P * 64);
+            T *dst = lds + ((k - 1) & 1) * (D * P * 64);
+#pragma unroll
+            for (int i = 0; i < DP; ++i) {
+                const int d = wave + kPreProd * i;
+                T s[P];
+#pragma unroll
+                for (int j = 0; j < P; ++j) s[j] = A::from((double)src[(d * P + j) * 64 + lane]);
+#pragma unroll
+                for (int j = 1; j < P; ++j) s[j] = A::add(s[j - 1], s[j]);
+                const T excl = A::template dpp<0x138, 0xf>(wave_scan<A>(s[P - 1]));   // wave_shr:1, zero in lane 0
+#pragma unroll
+                for (int j = 0; j < P; ++j) dst[(d * P + j) * 64 + lane] = A::add(excl, s[j]);
+            }
+        }
+        lds_barrier();
+    }
+}
+
+template <class A, int P>
+__device__ __forceinline__ void preint_consumer(const Window w, void *gout, const typename A::T *lds)
+{
+    using T = typename A::T;
+    constexpr int D = pre_rows<P>();
+    const int lane = threadIdx.x & 63, cb = lane * P;
+    uint32_t soff[P / 2];   // byte offset of each column pair in a window row; out of range past the width
+    T keep[P];              // 1 inside the window's width, 0 beyond (RS4 must see zeros there)
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int c = cb + j;
+        if (!(j & 1)) soff[j / 2] = c < w.w ? (uint32_t)(c * sizeof(T)) : 0x7ffffff0u;
+        keep[j] = A::from(c < w.w ? 1.0 : 0.0);
+    }
+    const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(
+        gout, 0, (int)((int64_t)w.h * w.w * sizeof(T)), kBufWord3);
+    T p90[P], g45p[P], gbp[P];   // RS3, and the previous row's RS2 / RS4, of the lane's columns
+#pragma unroll
+    for (int j = 0; j < P; ++j) p90[j] = g45p[j] = gbp[j] = A::zero();
+    const int nblk = (w.h + D - 1) / D;
+    for (int k = 0; k < nblk + 2; ++k) {
+        if (k >= 2) {   // block k - 2
+            const T *buf = lds + (k & 1) * (D * P * 64);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const T left = A::template dpp<0x138, 0xf>(g45p[P - 1]);   // g45[r-1][cb-1], zero in lane 0
+                const T right = A::template dpp<0x130, 0xf>(gbp[0]);       // gb[r-1][cb+P] (wave_shl:1), zero in lane 63
+#pragma unroll
+                for (int j = P - 1; j >= 0; --j) {   // descending: g45p[j - 1] still holds row r - 1
+                    const T g45 = A::s2add(buf[(d * P + j) * 64 + lane], j ? g45p[j - 1] : left);   // RS2
+                    p90[j] = A::add(g45, p90[j]);                                                  // RS3
+                    g45p[j] = g45;
+                }
+                T gb[P];
+#pragma unroll
+                for (int j = 0; j < P; ++j) gb[j] = A::mul01(A::s2add(p90[j], j + 1 < P ? gbp[j + 1] : right), keep[j]);   // RS4
+                const uint32_t roff = (uint32_t)(((k - 2) * D + d) * w.w * (int)sizeof(T));
+#pragma unroll
+                for (int j = 0; j < P; j += 2) {
+                    gbp[j] = gb[j];
+                    gbp[j + 1] = gb[j + 1];
+                    __builtin_amdgcn_raw_buffer_store_b128(A::pack2(gb[j], gb[j + 1]), out, roff + soff[j / 2], 0, 0);
+                }
+            }
+        }
+        lds_barrier();
+    }
+}
+
+template <class A, int IN, int P>
+__device__ __forceinline__ void sweep_window_split(const Job &J, int ch, const Window w, void *gout, typename A::T *lds)
+{
+    const int wave = threadIdx.x >> 6;   // uniform: 0 .. kPreProd - 1 RS1, then the consumer, then the loader
+    if (wave < kPreProd) {
+        preint_producer<A, P>(w, lds, wave);
+        return;
+    }
+    if (wave == kPreProd) {
+        preint_consumer<A, P>(w, gout, lds);
+        return;
+    }
+    // pair loads where all 64 P columns of the wave lie inside the image
+    const bool pairs = IN == kInF32 && J.C == 1 && w.c0 >= 0 && w.c0 + 64 * P <= J.W && (J.in_rs & 1) == 0 &&
+                       (reinterpret_cast<uintptr_t>(J.in) & 7) == 0;
+    if (IN == kInF32 && pairs) preint_loader<A, IN, P, IN == kInF32>(J, ch, w, lds);
+    else preint_loader<A, IN, P, false>(J, ch, w, lds);
+}
+
+// one work-group of kPreWaves waves per (tile, channel) window; the columns per
+// lane follow the window's width
+template <class A, int IN>
+__global__ __launch_bounds__(64 * kPreWaves) void k_preint(Job J)
+{
+    // RS1 buffers, then the input buffers (2 x D x P x 64 floats)
+    __shared__ typename A::T lds[kPreLds + kPreLds / 2];
     const int lt = blockIdx.x / J.C, ch = blockIdx.x - lt * J.C;
     const int tile = J.tr0 * J.ntc + lt;
     const Window w = window_of(J, tile);
     void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
-    sweep_window<A, IN, KC>(J, ch, w, gout, L);
+    const int p = (w.w + 63) / 64;   // uniform; <= kMaxWindow / 64 = 16
+    if (p <= 2) sweep_window_split<A, IN, 2>(J, ch, w, gout, lds);
+    else if (p <= 4) sweep_window_split<A, IN, 4>(J, ch, w, gout, lds);
+    else if (p <= 6) sweep_window_split<A, IN, 6>(J, ch, w, gout, lds);
+    else if (p <= 8) sweep_window_split<A, IN, 8>(J, ch, w, gout, lds);
+    else if (p <= 12) sweep_window_split<A, IN, 12>(J, ch, w, gout, lds);
+    else sweep_window_split<A, IN, 16>(J, ch, w, gout, lds);
 }
 
 template <class A, int KC>
@@ -818,41 +1044,27 @@ __global__ __launch_bounds__(kScanThreads + 64) void k_preint_window(Job J, int 
     sweep_window<A, IN, kScanChunks>(J, ch, w, g, L);
 }
 
-template <class A, int KC>
-hipError_t launch_preint_kc(const Job &j, int nb, hipStream_t s)
-{
-    if (j.in_type == kInF32)
-        hipLaunchKernelGGL((k_preint<A, kInF32, KC>), dim3(nb), dim3(kScanThreads + 64), 0, s, j);
-    else
-        hipLaunchKernelGGL((k_preint<A, kInU16, KC>), dim3(nb), dim3(kScanThreads + 64), 0, s, j);
-    return hipGetLastError();
-}
-
 template <class A>
 hipError_t launch_preint_t(const Job &j, hipStream_t s)
 {
     const int nb = (j.tr1 - j.tr0) * j.ntc * j.C;
     if (nb <= 0) return hipSuccess;
-    if (chunks_for(j.T, j.cap) == 1) return launch_preint_kc<A, 1>(j, nb, s);
-    return launch_preint_kc<A, kScanChunks>(j, nb, s);
+    if (j.in_type == kInF32) hipLaunchKernelGGL((k_preint<A, kInF32>), dim3(nb), dim3(64 * kPreWaves), 0, s, j);
+    else hipLaunchKernelGGL((k_preint<A, kInU16>), dim3(nb), dim3(64 * kPreWaves), 0, s, j);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 int64_t slot_elems_for(int T, int cap)
 {
-    const int64_t side = (int64_t)T + 2 * (int64_t)cap + 5;
+    const int64_t side = (int64_t)T + 2 * (int64_t)cap + 6;   // window sides are even (T is)
     return side * side;
-}
-
-int chunks_for(int T, int cap)
-{
-    return (T + 2 * cap + 5 + kScanCols - 1) / kScanCols;
 }
 
 int batch_chunks_for(int T, int cap)
 {
-    return (T + 2 * cap + 5 + kBatchCols - 1) / kBatchCols;
+    return (T + 2 * cap + 6 + kBatchCols - 1) / kBatchCols;
 }
 
 int scale_map_blocks(int64_t H, int64_t W)
