@@ -801,42 +801,47 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
     }
 }
 
-// Row sweep split over the waves of one work-group per window.  Lane l owns the
-// P adjacent columns l P .. l P + P - 1 (P 64 >= the window width, P even);
-// rows go in blocks of D, through a pipeline with one barrier per block:
-//   loader wave      : input rows of block k into an LDS buffer (its memory queue
-//                      holds loads only, kPreAhead blocks ahead, so it waits
-//                      exactly for the oldest);
+// Row sweep split over the waves of one work-group per window.  Lane l of the
+// compute waves owns the P adjacent columns l P .. l P + P - 1 (P 64 >= the
+// window width, P even); rows go in blocks of D, through a pipeline with one
+// barrier per block:
+//   loader wave      : input rows of block k into LDS (its memory queue holds
+//                      loads only, pre_ahead blocks ahead, so it waits exactly
+//                      for the oldest);
 //   kPreProd waves   : RS1 of block k - 1 (the lane's serial prefix, then the
 //                      wave prefix of the lane totals by DPP, added to it; rows
 //                      are independent, each wave takes every kPreProd-th) into
-//                      a second LDS buffer;
-//   consumer wave    : RS2..RS4 of block k - 2, row after row: RS2 and RS4 take
-//                      the previous row's value one column to the left / right
-//                      from the lane's registers or, at its first / last column,
-//                      from the neighbouring lane (wave shift by one lane, DPP);
-//                      RS3 stays in registers; results to the window.
+//                      an LDS block buffer;
+//   sum wave         : RS2..RS4 of block k - 2 in place, row after row: RS2 and
+//                      RS4 take the previous row's value one column to the left
+//                      / right from the lane's registers or, at its first / last
+//                      column, from the neighbouring lane (wave shift by one
+//                      lane, DPP); RS3 stays in registers;
+//   storer wave      : block k - 3 to the window.
 // Each wave alone would be bound by the latency of its instruction chains or of
-// memory; split this way the window's work runs on four SIMDs at once.
+// memory; split this way the window's work runs on several SIMDs at once.
 //
-// The last block runs past the window's last row: its loads read valid rows
-// (mapped into the image) and its stores fall outside the window's buffer
-// range, which the hardware drops, as it drops the stores of lanes' columns
-// beyond the window's width; so the blocks have no branch.  Results are written
-// as pairs of columns (16-byte stores: window widths and origins are even, P is
-// even); where the wave's columns are all inside the image and the image is one
-// f32 channel with an even row stride, inputs are read as pairs (8-byte loads).
+// LDS holds the compute waves' layout, [row][column in lane][lane]; the loader
+// and the storer move whole contiguous row segments (lane l takes the two
+// columns 2 l + 128 m, 2 l + 128 m + 1: 8-byte loads, 16-byte stores, every
+// access of a wave one contiguous run) and scatter / gather them there.  Input
+// pairs need a window inside the image, one f32 channel, an even row stride
+// (window origins are even); elsewhere the loader reads single columns through
+// the boundary rule.  The last block runs past the window's last row: its
+// loads read valid rows (mapped into the image) and its stores fall outside the
+// window's buffer range, which the hardware drops, as it drops the stores of
+// columns beyond the window's width (widths are even: pairs never straddle it).
 constexpr int kPreProd = 2;                          // RS1 waves per window
-constexpr int kPreAhead = 2;                         // blocks of input rows the loader has in flight
-constexpr int kPreWaves = kPreProd + 2;              // + loader + consumer
-constexpr int kPreLds = 2 * 8 * 8 * 64;              // T elements: 2 buffers x D x P x 64 (max over P)
+constexpr int kPreWaves = kPreProd + 3;              // + sum wave, storer, loader
+constexpr int kPreBuf = 8 * 8 * 64;                  // T elements of a block buffer: D x P x 64 (max over P)
 
 template <int P>
 constexpr int pre_rows() { return P <= 8 ? 8 : 4; }   // D: rows per block
-
-// Input buffer (floats) after the RS1 buffer: 2 x D x P x 64 values, [d][j][lane].
+template <int P>
+constexpr int pre_ahead() { return P <= 4 ? 2 : 1; }  // blocks of input rows the loader has in flight
+// LDS: three block buffers of sums (T), then two of input (float).
 template <class A>
-__device__ __forceinline__ float *pre_inbuf(typename A::T *lds) { return reinterpret_cast<float *>(lds + kPreLds); }
+__device__ __forceinline__ float *pre_inbuf(typename A::T *lds) { return reinterpret_cast<float *>(lds + 3 * kPreBuf); }
 
 template <class A, int IN, int P, bool PAIRS>
 __device__ __forceinline__ void preint_loader(const Job &J, int ch, const Window w, typename A::T *lds)
@@ -844,18 +849,21 @@ __device__ __forceinline__ void preint_loader(const Job &J, int ch, const Window
     static_assert(P % 2 == 0, "column pairs");
     static_assert(!PAIRS || IN == kInF32, "pair loads read f32 input");
     using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
-    constexpr int D = pre_rows<P>();
-    const int lane = threadIdx.x & 63, cb = lane * P;
+    constexpr int D = pre_rows<P>(), kPreAhead = pre_ahead<P>();
+    const int lane = threadIdx.x & 63;
     const int bnd = J.boundary;
     const E *in = static_cast<const E *>(J.in);
+    // value v of a row: column 2 lane + 128 (v / 2) + v % 2 (pairs) or lane + 64 v
     int32_t coff[P];
-    uint32_t cmask = 0;   // columns inside the window (and, zero rule, inside the image)
+    int16_t pos[P];       // its LDS position: (column % P) * 64 + column / P
+    uint32_t vmask = 0;   // inside the window (and, zero rule, inside the image)
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int c = cb + j;
+    for (int v = 0; v < P; ++v) {
+        const int c = PAIRS ? 2 * lane + 128 * (v / 2) + (v & 1) : lane + 64 * v;
         const int64_t C = w.c0 + c;
-        coff[j] = (int32_t)(ext_index(C, J.W, bnd) * J.C + ch);
-        if (c < w.w && (bnd != kBoundZero || (C >= 0 && C < J.W))) cmask |= 1u << j;
+        coff[v] = (int32_t)(ext_index(C, J.W, bnd) * J.C + ch);
+        pos[v] = (int16_t)((c % P) * 64 + c / P);
+        if (c < w.w && (bnd != kBoundZero || (C >= 0 && C < J.W))) vmask |= 1u << v;
     }
     E ring[kPreAhead][D][P];   // input rows of the next kPreAhead blocks
     auto issue = [&](int rr, E *dst) {   // rows past the window map to valid rows (values unused)
@@ -864,14 +872,14 @@ __device__ __forceinline__ void preint_loader(const Job &J, int ch, const Window
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<E *>(rowp + w.c0), 0, 64 * P * (int)sizeof(E), kBufWord3);
 #pragma unroll
-            for (int j = 0; j < P; j += 2) {
-                const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (cb + j) * 4, 0, 0));
-                dst[j] = v.x;
-                dst[j + 1] = v.y;
+            for (int m = 0; m < P / 2; ++m) {
+                const float2 x = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (2 * lane + 128 * m) * 4, 0, 0));
+                dst[2 * m] = x.x;
+                dst[2 * m + 1] = x.y;
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < P; ++j) dst[j] = rowp[coff[j]];
+            for (int v = 0; v < P; ++v) dst[v] = rowp[coff[v]];
         }
     };
 #pragma unroll
@@ -880,20 +888,20 @@ __device__ __forceinline__ void preint_loader(const Job &J, int ch, const Window
         for (int d = 0; d < D; ++d) issue(u * D + d, ring[u][d]);
     float *inb = pre_inbuf<A>(lds);
     const int nblk = (w.h + D - 1) / D;
-    for (int k0 = 0; k0 < nblk + 2; k0 += kPreAhead) {
+    for (int k0 = 0; k0 < nblk + 3; k0 += kPreAhead) {
 #pragma unroll
         for (int u = 0; u < kPreAhead; ++u) {   // block k comes from ring[k % kPreAhead]
             const int k = k0 + u;
-            if (k >= nblk + 2) break;   // uniform
+            if (k >= nblk + 3) break;   // uniform
             if (k < nblk) {
-                float *buf = inb + (k & 1) * (D * P * 64);
+                float *buf = inb + (k & 1) * kPreBuf;   // input buffers: kPreBuf floats each
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     const int64_t R = w.r0 + k * D + d;
                     const bool rin = bnd != kBoundZero || (R >= 0 && R < J.H);
 #pragma unroll
-                    for (int j = 0; j < P; ++j)
-                        buf[(d * P + j) * 64 + lane] = (rin && ((cmask >> j) & 1u)) ? (float)ring[u][d][j] : 0.f;
+                    for (int v = 0; v < P; ++v)
+                        buf[d * P * 64 + pos[v]] = (rin && ((vmask >> v) & 1u)) ? (float)ring[u][d][v] : 0.f;
                     issue((k + kPreAhead) * D + d, ring[u][d]);
                 }
             }
@@ -907,14 +915,14 @@ __device__ __forceinline__ void preint_producer(const Window w, typename A::T *l
 {
     using T = typename A::T;
     constexpr int D = pre_rows<P>(), DP = D / kPreProd;   // rows of a block, of them this wave's
-    static_assert(DP * kPreProd == D && 2 * D * P * 64 <= kPreLds, "block rows and LDS buffers");
+    static_assert(DP * kPreProd == D && D * P * 64 <= kPreBuf, "block rows and LDS buffers");
     const int lane = threadIdx.x & 63;
     const float *inb = pre_inbuf<A>(lds);
     const int nblk = (w.h + D - 1) / D;
-    for (int k = 0; k < nblk + 2; ++k) {
+    for (int k = 0; k < nblk + 3; ++k) {
         if (k >= 1 && k <= nblk) {   // block k - 1
-            const float *src = inb + ((k - 1) & 1) * (D * P * 64);
-            T *dst = lds + ((k - 1) & 1) * (D * P * 64);
+            const float *src = inb + ((k - 1) & 1) * kPreBuf;
+            T *dst = lds + ((k - 1) % 3) * kPreBuf;
 #pragma unroll
             for (int i = 0; i < DP; ++i) {
                 const int d = wave + kPreProd * i;
@@ -933,28 +941,21 @@ __device__ __forceinline__ void preint_producer(const Window w, typename A::T *l
 }
 
 template <class A, int P>
-__device__ __forceinline__ void preint_consumer(const Window w, void *gout, const typename A::T *lds)
+__device__ __forceinline__ void preint_sums(const Window w, typename A::T *lds)
 {
     using T = typename A::T;
     constexpr int D = pre_rows<P>();
     const int lane = threadIdx.x & 63, cb = lane * P;
-    uint32_t soff[P / 2];   // byte offset of each column pair in a window row; out of range past the width
-    T keep[P];              // 1 inside the window's width, 0 beyond (RS4 must see zeros there)
+    T keep[P];   // 1 inside the window's width, 0 beyond (RS4 must see zeros there)
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int c = cb + j;
-        if (!(j & 1)) soff[j / 2] = c < w.w ? (uint32_t)(c * sizeof(T)) : 0x7ffffff0u;
-        keep[j] = A::from(c < w.w ? 1.0 : 0.0);
-    }
-    const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(
-        gout, 0, (int)((int64_t)w.h * w.w * sizeof(T)), kBufWord3);
+    for (int j = 0; j < P; ++j) keep[j] = A::from(cb + j < w.w ? 1.0 : 0.0);
     T p90[P], g45p[P], gbp[P];   // RS3, and the previous row's RS2 / RS4, of the lane's columns
 #pragma unroll
     for (int j = 0; j < P; ++j) p90[j] = g45p[j] = gbp[j] = A::zero();
     const int nblk = (w.h + D - 1) / D;
-    for (int k = 0; k < nblk + 2; ++k) {
-        if (k >= 2) {   // block k - 2
-            const T *buf = lds + (k & 1) * (D * P * 64);
+    for (int k = 0; k < nblk + 3; ++k) {
+        if (k >= 2 && k <= nblk + 1) {   // block k - 2, RS1 replaced by RS4
+            T *buf = lds + ((k - 2) % 3) * kPreBuf;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const T left = A::template dpp<0x138, 0xf>(g45p[P - 1]);   // g45[r-1][cb-1], zero in lane 0
@@ -968,12 +969,45 @@ __device__ __forceinline__ void preint_consumer(const Window w, void *gout, cons
                 T gb[P];
 #pragma unroll
                 for (int j = 0; j < P; ++j) gb[j] = A::mul01(A::s2add(p90[j], j + 1 < P ? gbp[j + 1] : right), keep[j]);   // RS4
-                const uint32_t roff = (uint32_t)(((k - 2) * D + d) * w.w * (int)sizeof(T));
 #pragma unroll
-                for (int j = 0; j < P; j += 2) {
+                for (int j = 0; j < P; ++j) {
                     gbp[j] = gb[j];
-                    gbp[j + 1] = gb[j + 1];
-                    __builtin_amdgcn_raw_buffer_store_b128(A::pack2(gb[j], gb[j + 1]), out, roff + soff[j / 2], 0, 0);
+                    buf[(d * P + j) * 64 + lane] = gb[j];
+                }
+            }
+        }
+        lds_barrier();
+    }
+}
+
+template <class A, int P>
+__device__ __forceinline__ void preint_storer(const Window w, void *gout, const typename A::T *lds)
+{
+    using T = typename A::T;
+    constexpr int D = pre_rows<P>();
+    const int lane = threadIdx.x & 63;
+    // pair m of a row: columns c, c + 1 with c = 2 lane + 128 m (same owner lane c / P)
+    uint32_t soff[P / 2];   // byte offset in a window row; out of range past the width
+    int16_t pos[P / 2];     // LDS position of column c: (c % P) * 64 + c / P
+#pragma unroll
+    for (int m = 0; m < P / 2; ++m) {
+        const int c = 2 * lane + 128 * m;
+        soff[m] = c < w.w ? (uint32_t)(c * sizeof(T)) : 0x7ffffff0u;
+        pos[m] = (int16_t)((c % P) * 64 + c / P);
+    }
+    const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(
+        gout, 0, (int)((int64_t)w.h * w.w * sizeof(T)), kBufWord3);
+    const int nblk = (w.h + D - 1) / D;
+    for (int k = 0; k < nblk + 3; ++k) {
+        if (k >= 3) {   // block k - 3
+            const T *buf = lds + ((k - 3) % 3) * kPreBuf;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const uint32_t roff = (uint32_t)(((k - 3) * D + d) * w.w * (int)sizeof(T));
+#pragma unroll
+                for (int m = 0; m < P / 2; ++m) {
+                    const T *q = buf + d * P * 64 + pos[m];
+                    __builtin_amdgcn_raw_buffer_store_b128(A::pack2(q[0], q[64]), out, roff + soff[m], 0, 0);
                 }
             }
         }
@@ -984,16 +1018,11 @@ __device__ __forceinline__ void preint_consumer(const Window w, void *gout, cons
 template <class A, int IN, int P>
 __device__ __forceinline__ void sweep_window_split(const Job &J, int ch, const Window w, void *gout, typename A::T *lds)
 {
-    const int wave = threadIdx.x >> 6;   // uniform: 0 .. kPreProd - 1 RS1, then the consumer, then the loader
-    if (wave < kPreProd) {
-        preint_producer<A, P>(w, lds, wave);
-        return;
-    }
-    if (wave == kPreProd) {
-        preint_consumer<A, P>(w, gout, lds);
-        return;
-    }
-    // pair loads where all 64 P columns of the wave lie inside the image
+    const int wave = threadIdx.x >> 6;   // uniform: 0 .. kPreProd - 1 RS1, then sums, storer, loader
+    if (wave < kPreProd) return preint_producer<A, P>(w, lds, wave);
+    if (wave == kPreProd) return preint_sums<A, P>(w, lds);
+    if (wave == kPreProd + 1) return preint_storer<A, P>(w, gout, lds);
+    // pair loads where all 64 P columns lie inside the image
     const bool pairs = IN == kInF32 && J.C == 1 && w.c0 >= 0 && w.c0 + 64 * P <= J.W && (J.in_rs & 1) == 0 &&
                        (reinterpret_cast<uintptr_t>(J.in) & 7) == 0;
     if (IN == kInF32 && pairs) preint_loader<A, IN, P, IN == kInF32>(J, ch, w, lds);
@@ -1005,8 +1034,7 @@ __device__ __forceinline__ void sweep_window_split(const Job &J, int ch, const W
 template <class A, int IN>
 __global__ __launch_bounds__(64 * kPreWaves) void k_preint(Job J)
 {
-    // RS1 buffers, then the input buffers (2 x D x P x 64 floats)
-    __shared__ typename A::T lds[kPreLds + kPreLds / 2];
+    __shared__ typename A::T lds[4 * kPreBuf];   // 3 sum buffers, then 2 input buffers (floats)
     const int lt = blockIdx.x / J.C, ch = blockIdx.x - lt * J.C;
     const int tile = J.tr0 * J.ntc + lt;
     const Window w = window_of(J, tile);
