@@ -811,7 +811,8 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
 //   kPreProd waves   : RS1 of block k - 1 (the lane's serial prefix, then the
 //                      wave prefix of the lane totals by DPP, added to it; rows
 //                      are independent, each wave takes every kPreProd-th) into
-//                      an LDS block buffer;
+//                      an LDS block buffer (one wave measured faster than two
+//                      or four: four waves put one on each SIMD);
 //   sum wave         : RS2..RS4 of block k - 2 in place, row after row: RS2 and
 //                      RS4 take the previous row's value one column to the left
 //                      / right from the lane's registers or, at its first / last
@@ -831,7 +832,7 @@ __device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Wi
 // loads read valid rows (mapped into the image) and its stores fall outside the
 // window's buffer range, which the hardware drops, as it drops the stores of
 // columns beyond the window's width (widths are even: pairs never straddle it).
-constexpr int kPreProd = 2;                          // RS1 waves per window
+constexpr int kPreProd = 1;                          // RS1 waves per window
 constexpr int kPreWaves = kPreProd + 3;              // + sum wave, storer, loader
 constexpr int kPreBuf = 8 * 8 * 64;                  // T elements of a block buffer: D x P x 64 (max over P)
 
