@@ -166,13 +166,11 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     const int preint_of_pass[3] = {o.preint, o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint,
                                    o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint};
     std::string key = "n" + std::to_string(n);
-    int kc = 1;
     for (int i = 0; i < n; ++i) {
         Plan p = plans[i];
         p.off_tstat = off_fill[i];
         p.off_scales = off_scales[i];
         p.off_g = off_g[i];
-        kc = std::max(kc, batch_chunks_for(p.T, p.cap));
         svf_opts oi = o;
         Job base = base_job(&in[i], &fields[i], orders[i], &oi, p, ws);
         base.lut = lutj.lut;
@@ -225,7 +223,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
                 const int tb = 1 + pass * kMaxChannels + (ch - 1);
                 if (counts[tb] == 0) continue;
                 const Job *tab = B->d_jobs + tb * B->cap;
-                r = launch_preint_batch(tab, counts[tb], tot_tiles[tb], kPersistentPreint, preint_of_pass[pass], kc, s);
+                r = launch_preint_batch(tab, counts[tb], tot_tiles[tb], kPersistentPreint, preint_of_pass[pass], s);
                 if (r != hipSuccess) return r;
             }
             for (int ch = 1; ch <= kMaxChannels; ++ch) {

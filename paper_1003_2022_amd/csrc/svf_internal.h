@@ -132,12 +132,11 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
 // batched: `jobs` is a device table of n jobs; totals are the sums of the per-job counts
 // (persistent: `grid` work-groups loop over the work list)
 hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s);
-hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, int kc, hipStream_t s);
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s);
 hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,
                            hipStream_t s);
 
 int64_t slot_elems_for(int T, int cap);
-int batch_chunks_for(int T, int cap);   // 256-column chunks of the widest window (batched sweep)
 int scale_map_blocks(int64_t H, int64_t W);
 int fd_blocks_job(const Job &j);   // tile-major FD blocks, ragged edge tiles included
 

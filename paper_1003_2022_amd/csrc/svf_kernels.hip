@@ -702,104 +702,6 @@ __device__ __forceinline__ void sweep_window(const Job &J, int ch, const Window 
     }
 }
 
-// Row sweep for the batched launches (many small windows): one column per
-// thread in chunks of 256 columns, input rows loaded kBatchPrefetch ahead by the
-// compute threads themselves (unconditional loads at clamped addresses, masked
-// when consumed), wave totals and the previous row through LDS, one barrier per
-// row.  Same recursions as sweep_window, summed in the order of one column per
-// thread, so its g equals sweep_window's up to rounding.  With four waves and no
-// loader wave a work-group is small, so more windows run at once.
-constexpr int kBatchCols = kScanThreads;   // columns per chunk
-constexpr int kBatchChunks = kMaxWindow / kBatchCols;
-constexpr int kBatchPrefetch = 8;
-
-template <class A, int KC>
-struct alignas(16) ScanLds1 {
-    typename A::T p45[2][KC * kBatchCols + 2];   // previous row g45 at index c + 1 (index 0 stays zero)
-    typename A::T pb[2][KC * kBatchCols + 2];    // previous row g_b at index c (index >= w stays zero)
-    typename A::T wsum[2][KC][kScanThreads / 64];
-};
-
-template <class A, int IN, int KC>
-__device__ __forceinline__ void sweep_window_cols(const Job &J, int ch, const Window w, void *gout, ScanLds1<A, KC> &L)
-{
-    using T = typename A::T;
-    using E = typename std::conditional<IN == kInF32, float, unsigned short>::type;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int K = (w.w + kBatchCols - 1) / kBatchCols;   // <= KC
-    for (int i = t; i < KC * kBatchCols + 2; i += kScanThreads) {
-        L.p45[0][i] = A::zero(); L.pb[0][i] = A::zero();
-        L.p45[1][i] = A::zero(); L.pb[1][i] = A::zero();
-    }
-    const int bnd = J.boundary;
-    T p90[KC];
-    bool colin[KC];
-    int64_t colidx[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        p90[k] = A::zero();
-        const int c = k * kBatchCols + t;
-        const int64_t C = w.c0 + c;
-        colin[k] = k < K && c < w.w && (bnd != kBoundZero || (C >= 0 && C < J.W));
-        colidx[k] = ext_index(C, J.W, bnd) * J.C + ch;
-    }
-    const E *in = static_cast<const E *>(J.in);
-    E ring[kBatchPrefetch][KC];
-    auto issue = [&](int rr, E *dst) {
-        const int64_t R = ext_index(w.r0 + rr, J.H, bnd);
-        const E *rowp = in + R * J.in_rs;
-#pragma unroll
-        for (int k = 0; k < KC; ++k) dst[k] = rowp[colidx[k]];
-    };
-#pragma unroll
-    for (int d = 0; d < kBatchPrefetch; ++d) issue(d, ring[d]);
-    lds_barrier();
-    for (int rr0 = 0; rr0 < w.h; rr0 += kBatchPrefetch) {
-#pragma unroll
-        for (int d = 0; d < kBatchPrefetch; ++d) {
-            const int rr = rr0 + d;
-            if (rr >= w.h) break;   // uniform
-            const int64_t R = w.r0 + rr;
-            const bool rin = bnd != kBoundZero || (R >= 0 && R < J.H);
-            T v[KC];
-#pragma unroll
-            for (int k = 0; k < KC; ++k) v[k] = A::from((rin && colin[k]) ? (double)ring[d][k] : 0.0);
-            issue(rr + kBatchPrefetch, ring[d]);   // row rr + kBatchPrefetch, clamped (value unused past the end)
-            const int pp = rr & 1;                 // LDS buffer written by this row
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k < K) {
-                    v[k] = wave_scan<A>(v[k]);
-                    if (lane == 63) L.wsum[pp][k][wave] = v[k];
-                }
-            }
-            lds_barrier();
-            T carry = A::zero();
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                if (k < K) {
-                    T off = carry;
-#pragma unroll
-                    for (int q = 0; q < kScanThreads / 64; ++q) {
-                        const T ws = L.wsum[pp][k][q];
-                        if (q < wave) off = A::add(off, ws);
-                        carry = A::add(carry, ws);
-                    }
-                    const int c = k * kBatchCols + t;
-                    const T g0 = A::add(v[k], off);
-                    const T g45 = A::s2add(g0, L.p45[pp ^ 1][c]);        // RS2: sqrt2 g0 + g45[r-1][c-1]
-                    p90[k] = A::add(g45, p90[k]);                        // RS3: g45 + g90[r-1][c]
-                    const T gb = A::s2add(p90[k], L.pb[pp ^ 1][c + 1]);  // RS4: sqrt2 g90 + gb[r-1][c+1]
-                    if (c < w.w) {
-                        L.p45[pp][c + 1] = g45;
-                        L.pb[pp][c] = gb;
-                        A::store(gout, (int64_t)rr * w.w + c, gb);
-                    }
-                }
-            }
-        }
-    }
-}
 
 // Row sweep split over the waves of one work-group per window.  Lane l of the
 // compute waves owns the P adjacent columns l P .. l P + P - 1 (P 64 >= the
@@ -1030,16 +932,10 @@ __device__ __forceinline__ void sweep_window_split(const Job &J, int ch, const W
     else preint_loader<A, IN, P, false>(J, ch, w, lds);
 }
 
-// one work-group of kPreWaves waves per (tile, channel) window; the columns per
-// lane follow the window's width
+// the columns per lane follow the window's width
 template <class A, int IN>
-__global__ __launch_bounds__(64 * kPreWaves) void k_preint(Job J)
+__device__ __forceinline__ void preint_window(const Job &J, int ch, const Window w, void *gout, typename A::T *lds)
 {
-    __shared__ typename A::T lds[4 * kPreBuf];   // 3 sum buffers, then 2 input buffers (floats)
-    const int lt = blockIdx.x / J.C, ch = blockIdx.x - lt * J.C;
-    const int tile = J.tr0 * J.ntc + lt;
-    const Window w = window_of(J, tile);
-    void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
     const int p = (w.w + 63) / 64;   // uniform; <= kMaxWindow / 64 = 16
     if (p <= 2) sweep_window_split<A, IN, 2>(J, ch, w, gout, lds);
     else if (p <= 4) sweep_window_split<A, IN, 4>(J, ch, w, gout, lds);
@@ -1049,10 +945,24 @@ __global__ __launch_bounds__(64 * kPreWaves) void k_preint(Job J)
     else sweep_window_split<A, IN, 16>(J, ch, w, gout, lds);
 }
 
-template <class A, int KC>
-__global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, int n, int total)
+// one work-group of kPreWaves waves per (tile, channel) window
+template <class A, int IN>
+__global__ __launch_bounds__(64 * kPreWaves) void k_preint(Job J)
 {
-    __shared__ ScanLds1<A, KC> L;
+    __shared__ typename A::T lds[4 * kPreBuf];   // 3 sum buffers, then 2 input buffers (floats)
+    const int lt = blockIdx.x / J.C, ch = blockIdx.x - lt * J.C;
+    const int tile = J.tr0 * J.ntc + lt;
+    const Window w = window_of(J, tile);
+    void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
+    preint_window<A, IN>(J, ch, w, gout, lds);
+}
+
+// the batched launches: windows of every image of the table, one work-group
+// each in turn (grid-stride)
+template <class A>
+__global__ __launch_bounds__(64 * kPreWaves) void k_preint_batch(const Job *jobs, int n, int total)
+{
+    __shared__ typename A::T lds[4 * kPreBuf];
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 0));
         const Job &J = jobs[j];
@@ -1060,9 +970,9 @@ __global__ __launch_bounds__(kScanThreads) void k_preint_batch(const Job *jobs, 
         const int tile = lt / J.C, ch = lt - tile * J.C;
         const Window w = window_of(J, tile);
         void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
-        if (J.in_type == kInU16) sweep_window_cols<A, kInU16, KC>(J, ch, w, gout, L);
-        else sweep_window_cols<A, kInF32, KC>(J, ch, w, gout, L);
-        lds_barrier();   // the shared records are reused by the next window
+        if (J.in_type == kInU16) preint_window<A, kInU16>(J, ch, w, gout, lds);
+        else preint_window<A, kInF32>(J, ch, w, gout, lds);
+        lds_barrier();   // the buffers are reused by the next window
     }
 }
 
@@ -1091,10 +1001,6 @@ int64_t slot_elems_for(int T, int cap)
     return side * side;
 }
 
-int batch_chunks_for(int T, int cap)
-{
-    return (T + 2 * cap + 6 + kBatchCols - 1) / kBatchCols;
-}
 
 int scale_map_blocks(int64_t H, int64_t W)
 {
@@ -1170,26 +1076,16 @@ hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int 
     return hipGetLastError();
 }
 
-hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, int kc, hipStream_t s)
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
     grid = std::max(1, std::min(grid, total_tiles));
-#define SVF_PB(A, KC) hipLaunchKernelGGL((k_preint_batch<A, KC>), dim3(grid), dim3(kScanThreads), 0, s, jobs, n, total_tiles)
-#define SVF_PB_KC(A)              \
-    switch (kc) {                 \
-    case 1: SVF_PB(A, 1); break;  \
-    case 2: SVF_PB(A, 2); break;  \
-    case 3: SVF_PB(A, 3); break;  \
-    default: SVF_PB(A, 4); break; \
-    }
     switch (preint) {
-    case kPreF64: SVF_PB_KC(ArF64); break;
-    case kPreF32C: SVF_PB_KC(ArF32C); break;
-    case kPreI64: SVF_PB_KC(ArI64); break;
+    case kPreF64: hipLaunchKernelGGL((k_preint_batch<ArF64>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles); break;
+    case kPreF32C: hipLaunchKernelGGL((k_preint_batch<ArF32C>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles); break;
+    case kPreI64: hipLaunchKernelGGL((k_preint_batch<ArI64>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles); break;
     default: return hipErrorInvalidValue;
     }
-#undef SVF_PB_KC
-#undef SVF_PB
     return hipGetLastError();
 }
 

@@ -141,7 +141,7 @@ Server *srv(svf_ctx *ctx) { return static_cast<Server *>(ctx->server); }
 
 // Launch one step from the tables in `b`; returns false on a HIP error.
 bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *counts, const int *tot_tiles,
-                 const int *tot_blk, int kc)
+                 const int *tot_blk)
 {
     hipError_t e = hipMemcpyAsync(b.d, b.h, sizeof(Job) * kTables * S->cap, hipMemcpyHostToDevice, S->stream);
     if (e != hipSuccess) return false;
@@ -154,7 +154,7 @@ bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *coun
     if (e == hipSuccess && nsmap) e = launch_scale_map_batch(b.d, nsmap, tot_smap, kPersistentScale, S->lut != nullptr, S->stream);
     for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
         if (counts[ch]) e = launch_preint_batch(b.d + ch * S->cap, counts[ch], tot_tiles[ch], kPersistentPreint,
-                                                S->cfg.opts.preint, kc, S->stream);
+                                                S->cfg.opts.preint, S->stream);
     for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
         if (counts[ch]) e = launch_fd_batch(b.d + ch * S->cap, counts[ch], tot_blk[ch], kPersistentFd,
                                             S->cfg.opts.preint, S->cfg.opts.fd_fp32, ch, S->stream);
@@ -262,7 +262,7 @@ void loop(Server *S)
         }
         // ---- build the tables (only this thread writes q.pass / q.off) ----
         int counts[kTables] = {}, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
-        int tot_smap = 0, kc = 1;
+        int tot_smap = 0;
         int nsmap = 0;
         for (auto &pr : running) {
             const uint64_t id = pr.first;
@@ -272,7 +272,6 @@ void loop(Server *S)
             pp.off_tstat = q.off + p.off_tstat;
             pp.off_scales = q.off + p.off_scales;
             pp.off_g = q.off + p.off_g;
-            kc = std::max(kc, batch_chunks_for(p.T, p.cap));
             Job base = base_job(&q.r.in, &q.r.field, q.r.order, &S->cfg.opts, pp, S->arena_base);
             if (S->lut) {
                 base.lut = S->lut;
@@ -303,7 +302,7 @@ void loop(Server *S)
             if (q.pass == q.r.order) b.finishing.push_back(id);
             b.running.push_back(id);
         }
-        if (!launch_step(S, b, nsmap, tot_smap, counts, tot_tiles, tot_blk, kc)) {
+        if (!launch_step(S, b, nsmap, tot_smap, counts, tot_tiles, tot_blk)) {
             std::lock_guard<std::mutex> lk(S->mu);
             S->err = "step launch failed";
         }
