@@ -926,8 +926,8 @@ __device__ __forceinline__ void sweep_window_split(const Job &J, int ch, const W
     if (wave == kPreProd) return preint_sums<A, P>(w, lds);
     if (wave == kPreProd + 1) return preint_storer<A, P>(w, gout, lds);
     // pair loads where all 64 P columns lie inside the image
-    const bool pairs = IN == kInF32 && J.C == 1 && w.c0 >= 0 && w.c0 + 64 * P <= J.W && (J.in_rs & 1) == 0 &&
-                       (reinterpret_cast<uintptr_t>(J.in) & 7) == 0;
+    const bool pairs = IN == kInF32 && J.C == 1 && w.c0 >= 0 && (w.c0 & 1) == 0 && w.c0 + 64 * P <= J.W &&
+                       (J.in_rs & 1) == 0 && (reinterpret_cast<uintptr_t>(J.in) & 7) == 0;
     if (IN == kInF32 && pairs) preint_loader<A, IN, P, IN == kInF32>(J, ch, w, lds);
     else preint_loader<A, IN, P, false>(J, ch, w, lds);
 }
@@ -974,6 +974,14 @@ __global__ __launch_bounds__(64 * kPreWaves) void k_preint_batch(const Job *jobs
         else preint_window<A, kInF32>(J, ch, w, gout, lds);
         lds_barrier();   // the buffers are reused by the next window
     }
+}
+
+// a caller's window on the pipelined sweep (even width, 16-byte aligned output)
+template <class A, int IN>
+__global__ __launch_bounds__(64 * kPreWaves) void k_preint_window_split(Job J, int ch, Window w, void *g)
+{
+    __shared__ typename A::T lds[4 * kPreBuf];
+    preint_window<A, IN>(J, ch, w, g, lds);
 }
 
 template <class A, int IN>
@@ -1049,6 +1057,29 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
 {
     Window win;
     win.r0 = r0; win.c0 = c0; win.h = h; win.w = w;
+    // the pipelined sweep needs an even width (its stores move column pairs), a
+    // 16-byte aligned output and byte offsets in 32 bits; other windows take the
+    // one-work-group sweep with a loader wave
+    if ((w & 1) == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0 && (int64_t)h * w * 8 < ((int64_t)1 << 31) - 65536) {
+#define SVF_PW(A, IN) hipLaunchKernelGGL((k_preint_window_split<A, IN>), dim3(1), dim3(64 * kPreWaves), 0, s, j, channel, win, g)
+        switch (j.preint) {
+        case kPreF64:
+            if (j.in_type == kInF32) SVF_PW(ArF64, kInF32);
+            else SVF_PW(ArF64, kInU16);
+            break;
+        case kPreF32C:
+            if (j.in_type == kInF32) SVF_PW(ArF32C, kInF32);
+            else SVF_PW(ArF32C, kInU16);
+            break;
+        case kPreI64:
+            if (j.in_type != kInU16) return hipErrorInvalidValue;
+            SVF_PW(ArI64, kInU16);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+#undef SVF_PW
+        return hipGetLastError();
+    }
     switch (j.preint) {
     case kPreF64:
         if (j.in_type == kInF32) hipLaunchKernelGGL((k_preint_window<ArF64, kInF32>), dim3(1), dim3(kScanThreads + 64), 0, s, j, channel, win, g);

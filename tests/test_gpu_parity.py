@@ -61,7 +61,10 @@ def gpu_filter(ctx, img, fld, kind, order, **opts):
 
 # ----------------------------------------------------------------------------- running sums
 
-@pytest.mark.parametrize("win", [(-5, -7, 90, 130), (0, 0, 64, 64), (40, 250, 70, 300), (-3, 290, 40, 60)])
+# even widths take the pipelined sweep (widths up to 128, 256, 384, 512, 768 and
+# 1024 columns select its column counts per lane); odd widths the other sweep
+@pytest.mark.parametrize("win", [(-5, -7, 90, 130), (0, 0, 64, 64), (40, 250, 70, 300), (-3, 290, 40, 60),
+                                 (5, 7, 33, 77), (-9, -100, 50, 700), (2, 3, 20, 1000)])
 def test_preint_i64_bit_exact(ctx, win):
     img = I.uniform_image(120, 333, 3001, "u16")
     r0, c0, h, w = win
@@ -84,9 +87,12 @@ def test_preint_i64_bit_exact_large_wrapping(ctx):
         assert np.array_equal(g.cpu().numpy(), ref), (r0, c0)
 
 
-def test_preint_f64_and_f32c(ctx):
+# windows: crossing the image's corner, inside it with an even origin (paired
+# input loads), with an odd origin (single loads), and an odd width
+@pytest.mark.parametrize("win", [(-4, -6, 170, 230), (3, 10, 140, 128), (3, 11, 140, 128), (-2, 5, 60, 61)])
+def test_preint_f64_and_f32c(ctx, win):
     img = I.uniform_image(150, 200, 3002)
-    r0, c0, h, w = -4, -6, 170, 230
+    r0, c0, h, w = win
     ref = oracle.preint_window_f64(img, r0, c0, h, w)
     g = torch.empty((h, w), dtype=torch.float64, device=DEV)
     P.svf_preintegrate(ctx, P.image_of(to_dev(img)), 0, r0, c0, h, w, P.SVF_PRE_F64, g)
@@ -96,7 +102,7 @@ def test_preint_f64_and_f32c(ctx):
     e64 = np.abs(g.cpu().numpy() - ref).max() / np.abs(ref).max()
     pair = g2.cpu().numpy().astype(np.float64)
     e32 = np.abs(pair[..., 0] + pair[..., 1] - ref).max() / np.abs(ref).max()
-    print(f"preint rel err: f64 {e64:.2e}  f32c {e32:.2e}")
+    print(f"preint {win} rel err: f64 {e64:.2e}  f32c {e32:.2e}")
     assert e64 < 1e-14
     assert e32 < 1e-11
 
@@ -147,6 +153,19 @@ def test_filter_ragged_tiles(ctx, shape, tile):
     got, rep = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, 2, tile=tile)
     ref = oracle.filter(img, fld, oracle.FIELD_SRT3, 2)
     check_close(got, ref, what=f"{H}x{W} tile {tile}")
+
+
+@pytest.mark.parametrize("sigma", [60.0, 110.0])
+def test_filter_wide_windows(ctx, sigma):
+    # 256-px tiles and reaches of 178 / 326 px: windows 618 / 914 columns wide,
+    # the widest column counts per lane of the pipelined pre-integration
+    H, W = 520, 600
+    img = I.uniform_image(H, W, 3025)
+    fld = I.constant_srt_field(H, W, sigma)
+    got, rep = gpu_filter(ctx, img, fld, P.SVF_FIELD_SRT3, 1, tile=256, max_reach_px=381)
+    assert rep.overflow_px == 0
+    ref = oracle.filter(img, fld, oracle.FIELD_SRT3, 1)
+    check_close(got, ref, what=f"sigma {sigma} 256-px tiles")
 
 
 def test_filter_white_scales_and_multichannel(ctx):
