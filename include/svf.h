@@ -206,9 +206,8 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
  * counts).  With use_graph != 0 the launch sequence is captured once per
  * distinct shape set into a HIP graph and replayed.  Results equal n
  * svf_filter calls with the same options (opts.tile 0 means 256 here) up to
- * rounding: the batched pre-integration (many small windows) keeps one column
- * per thread and sums in another order than the single-image sweep.  Returns
- * after enqueueing (the descriptor upload is stream-ordered).
+ * rounding.  Returns after enqueueing (the descriptor upload is
+ * stream-ordered).
  */
 svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
                             const svf_opts *opts, svf_image *out, hipStream_t stream, int use_graph);

@@ -2,7 +2,7 @@
 CPU FP64 oracle, whose every pass is the direct sum over the image extended by
 the same rule.  Same tolerances as the zero rule: per pixel 1e-5 relative (FP64
 sums), RMS 1e-6; batched, banded and served launches agree with svf_filter
-(bit for bit for bands, 1e-6 for the batched sums, which add in another order).
+(bit for bit for bands, 1e-6 for the batched launch).
 """
 import ctypes as C
 
