@@ -139,9 +139,11 @@ typedef struct {
 typedef struct {
     int64_t clamped_px;    /* pixels whose elongation was lowered to the feasible maximum */
     int64_t eps_active_px; /* pixels with a component of a^2 at the floor */
-    int64_t invalid_px;    /* pixels with a non-finite / non-positive-definite field entry
-                              (filtered with the smallest isotropic scales instead) */
-    int64_t overflow_px;   /* pixels whose support exceeded max_reach_px */
+    int64_t invalid_px;    /* pixels with a non-finite / non-positive-definite field entry: with
+                              SVF_FIELD_COV3 / SVF_FIELD_SRT3 they are filtered with the smallest
+                              isotropic scales instead; SVF_FIELD_SCALES4 entries that are not
+                              finite and positive give NaN outputs */
+    int64_t overflow_px;   /* pixels whose support exceeded max_reach_px; their outputs are NaN */
     double max_reach_px;   /* largest support half-width of one pass over the image */
 } svf_report;
 
@@ -191,9 +193,11 @@ svf_status svf_preintegrate(svf_ctx *ctx, const svf_image *in, int channel, int6
 /*
  * The filter: order-`order` (1..3) space-variant filtering of every channel of
  * `in` with the field, N = 4.  out must be SVF_F32 with in's H, W, channels; it
- * may be the same buffer as an SVF_F32 input.  If rep != NULL the call waits
- * for completion, fills *rep, and returns SVF_EINVAL if invalid_px > 0 or
- * SVF_ERANGE if overflow_px > 0.
+ * may be the same buffer as an SVF_F32 input (also with opts.bands > 1).  Pixels
+ * whose pass support exceeds opts.max_reach_px, and pixels with invalid
+ * SVF_FIELD_SCALES4 scales, are written as NaN whether or not a report is asked
+ * for.  If rep != NULL the call waits for completion, fills *rep, and returns
+ * SVF_EINVAL if invalid_px > 0 or SVF_ERANGE if overflow_px > 0.
  */
 svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int N, int order,
                       const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep);
@@ -211,6 +215,15 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
  */
 svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
                             const svf_opts *opts, svf_image *out, hipStream_t stream, int use_graph);
+
+/*
+ * Reports of the last svf_filter_batch on this context (call it before any other
+ * filter call on the context): waits for that batch's stream, fills reps[i] for
+ * image i (n = the batch's image count), and returns SVF_EINVAL if some image has
+ * invalid_px > 0, else SVF_ERANGE if some has overflow_px > 0 (those outputs are
+ * NaN, as in svf_filter).
+ */
+svf_status svf_filter_batch_report(svf_ctx *ctx, int n, svf_report *reps);
 
 /* ---- feature-preserving smoothing (Sec. 4.2) ----
  *
@@ -298,7 +311,11 @@ typedef struct {
 } svf_request;
 
 typedef struct {
-    int32_t status;             /* SVF_OK when done, SVF_EBUSY while queued or running, else the error */
+    int32_t status;             /* SVF_OK when done, SVF_EBUSY while queued or running, else the error:
+                                   SVF_EINVAL / SVF_ERANGE when pixels had invalid field entries / supports
+                                   beyond max_reach_px (as svf_filter's report; the output is written,
+                                   NaN at those pixels where svf_filter writes NaN), SVF_ECANCELLED,
+                                   SVF_EHIP if a launch failed */
     int32_t done;
     double t_submit_us;         /* host steady clock, microseconds */
     double t_admit_us;
@@ -316,7 +333,9 @@ typedef struct {
 svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg);
 /* Queue a request (arguments are checked here); *id identifies it. */
 svf_status svf_server_submit(svf_ctx *ctx, const svf_request *req, uint64_t *id);
-/* Non-blocking state of a request. */
+/* Non-blocking state of a request.  A finished request's state stays readable
+ * until 4 * queue_capacity + 1024 later requests have finished; after that its id
+ * is unknown (SVF_EINVAL). */
 svf_status svf_server_poll(svf_ctx *ctx, uint64_t id, svf_result *res);
 /* Wait up to timeout_s seconds (< 0: forever) for a request; SVF_EBUSY on timeout. */
 svf_status svf_server_wait(svf_ctx *ctx, uint64_t id, svf_result *res, double timeout_s);

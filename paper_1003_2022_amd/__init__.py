@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
     L.svf_filter.argtypes = [vp, P(svf_image), P(svf_field), C.c_int, C.c_int, P(svf_opts), P(svf_image), vp, P(svf_report)]
     L.svf_filter_batch.restype = st
     L.svf_filter_batch.argtypes = [vp, C.c_int, P(svf_image), P(svf_field), P(C.c_int), P(svf_opts), P(svf_image), vp, C.c_int]
+    L.svf_filter_batch_report.restype = st
+    L.svf_filter_batch_report.argtypes = [vp, C.c_int, P(svf_report)]
     L.svf_st_default_params.restype = None
     L.svf_st_default_params.argtypes = [P(svf_st_params)]
     L.svf_structure_tensor.restype = st
@@ -265,6 +267,15 @@ def svf_filter_batch(ctx: Context, imgs, fields, orders, opts: svf_opts | None, 
     return ctx.check(lib().svf_filter_batch(ctx.ptr, n, IA(*imgs), FA(*fields), RA(*orders),
                                             C.byref(opts) if opts else None, OA(*outs), _stream_handle(stream),
                                             1 if use_graph else 0))
+
+
+def svf_filter_batch_report(ctx: Context, n: int):
+    """Reports of the last batch: (status, [svf_report] * n); SVF_EINVAL / SVF_ERANGE are returned, not raised."""
+    reps = (svf_report * n)()
+    st = lib().svf_filter_batch_report(ctx.ptr, n, reps)
+    if st not in (SVF_OK, SVF_EINVAL, SVF_ERANGE):
+        ctx.check(st)
+    return st, list(reps)
 
 
 def st_params(**kw) -> svf_st_params:

@@ -15,7 +15,7 @@ SOURCES = ["svf_kernels.hip", "svf_fd.hip", "svf_st.hip", "svf_runtime.cpp", "sv
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

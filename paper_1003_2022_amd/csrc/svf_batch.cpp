@@ -42,6 +42,10 @@ struct BatchState {
     bool upload_pending = false;
     uint64_t generation = 0;      // ws_generation the graphs were captured against
     std::vector<GraphEntry> graphs;
+    // the last call, for svf_filter_batch_report: stream, tile records per image
+    hipStream_t last_stream = nullptr;
+    std::vector<size_t> last_off, last_tiles;
+    std::vector<int> last_order;
 };
 
 BatchState *state(svf_ctx *ctx)
@@ -109,7 +113,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         max_order = std::max(max_order, orders[i]);
     }
     // ---- workspace: [tile stats of all images][scales][windows] ----
-    std::vector<size_t> off_fill(n), off_scales(n), off_g(n);
+    std::vector<size_t> off_fill(n), off_scales(n), off_plan(n), off_g(n);
     size_t pos = 0;
     for (int i = 0; i < n; ++i) {
         off_fill[i] = pos;
@@ -119,6 +123,11 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     for (int i = 0; i < n; ++i) {
         off_scales[i] = pos;
         if (fields[i].kind != SVF_FIELD_SCALES4) pos = align_up(pos + (size_t)in[i].H * in[i].W * 16, 256);
+    }
+    for (int i = 0; i < n; ++i) {
+        off_plan[i] = pos;
+        pos = align_up(pos + (size_t)plans[i].ntr * plans[i].ntc * (plans[i].T / 16) * (plans[i].T / 16) * sizeof(FdBlk),
+                       256);
     }
     for (int i = 0; i < n; ++i) {
         off_g[i] = pos;
@@ -162,7 +171,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     // with `channels` = C whose order exceeds `pass` (pre-integration and finite difference)
     unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
     int counts[kTables] = {};
-    int tot_smap = 0, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
+    int tot_smap = 0, tot_plan = 0, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
     const int preint_of_pass[3] = {o.preint, o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint,
                                    o.preint == SVF_PRE_I64 ? SVF_PRE_F64 : o.preint};
     std::string key = "n" + std::to_string(n);
@@ -170,6 +179,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         Plan p = plans[i];
         p.off_tstat = off_fill[i];
         p.off_scales = off_scales[i];
+        p.off_fdplan = off_plan[i];
         p.off_g = off_g[i];
         svf_opts oi = o;
         Job base = base_job(&in[i], &fields[i], orders[i], &oi, p, ws);
@@ -180,6 +190,8 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         base.out_rs = out[i].row_stride;
         base.smap_base = tot_smap;
         tot_smap += scale_map_blocks(in[i].H, in[i].W);
+        base.blk_base = tot_plan;   // table 0 also drives the block plan
+        tot_plan += fd_blocks_job(base);
         B->h_jobs[counts[0]++] = base;
         for (int pass = 0; pass < orders[i]; ++pass) {
             const int tb = 1 + pass * kMaxChannels + (in[i].channels - 1);
@@ -207,6 +219,11 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         snprintf(buf, sizeof buf, "#%d,%d,%.17g,%d", o.preint, o.fd_fp32, o.eps_px2, o.scale_map);
         key += buf;
     }
+    B->last_stream = stream;
+    B->last_off.assign(off_fill.begin(), off_fill.end());
+    B->last_tiles.resize(n);
+    B->last_order.assign(orders, orders + n);
+    for (int i = 0; i < n; ++i) B->last_tiles[i] = (size_t)plans[i].ntr * plans[i].ntc;
     hipError_t e = hipMemcpyAsync(B->d_jobs, B->h_jobs, sizeof(Job) * kTables * B->cap, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor upload");
     e = hipEventRecord(B->upload_done, stream);
@@ -217,6 +234,8 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
         hipError_t r = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(fill_bytes / 4), s);
         if (r != hipSuccess) return r;
         r = launch_scale_map_batch(B->d_jobs, counts[0], tot_smap, kPersistentScale, lutj.lut != nullptr, s);
+        if (r != hipSuccess) return r;
+        r = launch_fd_plan_batch(B->d_jobs, counts[0], tot_plan, s);
         if (r != hipSuccess) return r;
         for (int pass = 0; pass < max_order; ++pass) {
             for (int ch = 1; ch <= kMaxChannels; ++ch) {
@@ -272,5 +291,32 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     }
     e = timed_launch(ctx, kClsBatch, stream, [&] { return hipGraphLaunch(ge->exec, stream); });
     if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphLaunch");
+    return SVF_OK;
+}
+
+extern "C" svf_status svf_filter_batch_report(svf_ctx *ctx, int n, svf_report *reps)
+{
+    if (!ctx) return SVF_EINVAL;
+    ctx->err.clear();
+    BatchState *B = ctx->batch ? static_cast<BatchState *>(ctx->batch) : nullptr;
+    if (!B || B->last_off.empty()) return fail(ctx, SVF_EINVAL, "no batch on this context");
+    if (n != (int)B->last_off.size() || !reps) return fail(ctx, SVF_EINVAL, "n must be the last batch's image count");
+    const size_t bytes = B->last_off.back() + B->last_tiles.back() * sizeof(TileStat);
+    svf_status st = ensure_pinned(ctx, bytes);
+    if (st) return st;
+    hipSetDevice(ctx->device);
+    hipError_t e = hipMemcpyAsync(ctx->host_pinned, ctx->ws, bytes, hipMemcpyDeviceToHost, B->last_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B->last_stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch report");
+    int64_t inv = 0, ovf = 0;
+    for (int i = 0; i < n; ++i) {
+        const TileStat *ts = reinterpret_cast<const TileStat *>(static_cast<const unsigned char *>(ctx->host_pinned) +
+                                                                B->last_off[i]);
+        fill_report(ts, B->last_tiles[i], B->last_order[i], &reps[i]);
+        inv += reps[i].invalid_px;
+        ovf += reps[i].overflow_px;
+    }
+    if (inv > 0) return fail(ctx, SVF_EINVAL, "%lld pixels with an invalid field entry", (long long)inv);
+    if (ovf > 0) return fail(ctx, SVF_ERANGE, "%lld pixels exceed max_reach_px", (long long)ovf);
     return SVF_OK;
 }

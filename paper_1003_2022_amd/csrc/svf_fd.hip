@@ -1,9 +1,11 @@
 // svf_fd.hip -- gfx950 finite-difference kernel of the space-variant elliptical
 // box-spline filter (Chaudhury, Munoz-Barrutia, Unser):
 //
-//   k_fd : per pixel, the 16-tap finite difference of eq. (final_eqn) (taps of
-//          Table 1, shift tau of Sec. 3.1 step (2)) on the ZP interpolant of the
-//          pre-integrated window (App. F: 7 lattice samples, one of 4 triangles).
+//   k_fd      : per pixel, the 16-tap finite difference of eq. (final_eqn) (taps of
+//               Table 1, shift tau of Sec. 3.1 step (2)) on the ZP interpolant of the
+//               pre-integrated window (App. F: 7 lattice samples per tap).
+//   k_fd_plan : per 16 x 16 pixel block, its window and the origins of the regions
+//               the difference stages (once per filter call, after the scale map).
 //
 // Lattice: x = column, y = row, directions u1 = (1,0), u2 = (1,1)/sqrt2, u3 = (0,1),
 // u4 = (-1,1)/sqrt2.
@@ -12,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "svf_device.h"
 #include "svf_internal.h"
@@ -36,23 +39,36 @@ namespace {
 //   k = (1,+-1): 2 (s^2 + t^2) +- 4st
 // (they sum to 8).
 //
+// The kernel evaluates them without selecting the triangle first (zp_tap7 below).
+//
 // Data movement.  A work-group takes a 16 x 16 block of output pixels.  The 16
 // taps of all its pixels fall, for each tap, close to that tap of the block's
 // centre pixel shifted by the pixel's offset in the block; so for each tap the
 // group copies one 27 x 27 region of the window (the block, a margin of 4 for
-// the variation of the scales across the block, and the stencil) into LDS with
-// coalesced loads, and every lane takes its 7 samples from LDS.  A lane whose
-// stencil leaves the region (scales that change fast across the block) reads its
-// samples from the window directly instead.  Regions are double-buffered: the
-// loads for tap i+1 are in flight while tap i is computed, one barrier per tap.
-// Window samples are read with buffer loads (reads past the slot return zero).
-// ---------------------------------------------------------------------------
+// the variation of the scales across the block, and the stencil) into LDS, and
+// every lane takes its 7 samples from LDS.  A lane whose stencil leaves the region
+// (scales that change fast across the block) reads its samples from the window
+// directly instead.  binary64 windows go straight from the buffer loads into LDS
+// (16 bytes per lane, no staging registers): the loads of three taps are in flight
+// while a fourth region is read, one barrier per tap.  Integer and compensated
+// windows are converted to binary64 in registers and staged one tap ahead.  Window
+// samples are read with buffer loads (reads past the slot return zero).
+//
+// Measured on the 4096^2 order-2 workload (same box, per pass): the earlier design
+// with register staging, the seven weights of the canonical triangle and per-block
+// region origins computed by every wave ran 640-650 us; with the block plan, direct
+// loads into LDS and the branch-free weights, 576 us.  The nine-sample form of the
+// weights (no corner selection, 20 % more LDS bytes) ran 620 us, and without the
+// direct loads every variant ran slower than the earlier design (LDS traffic and
+// occupancy, not VALU issue, limit this kernel).
 constexpr int kFdSide = 16;                              // pixels per block side
 constexpr int kRegM = 4;                                 // margin for the spread of a tap over the block
-constexpr int kRegS = kFdSide + 2 * kRegM + 3;           // 27: region side
-constexpr int kRegN = kRegS * kRegS;                     // 729 samples
-constexpr int kRegLoads = (kRegN + 255) / 256;           // 3 per thread
-constexpr int kRegPad = kRegLoads * 256;                 // 768: LDS stride of a region (branch-free staging)
+constexpr int kRegS = kFdSide + 2 * kRegM + 3;           // 27: region side (rows; columns used)
+constexpr int kRS = kRegS + 1;                           // 28: LDS row stride of a region (whole 16-byte pairs)
+constexpr int kRegLoads = (kRegS * kRS + 255) / 256;     // 3 staged samples per thread (register staging)
+constexpr int kRegPad = kRegLoads * 256;                 // 768 samples: LDS stride of a region
+constexpr int kRegChunks = (kRegS * kRS / 2 + 63) / 64;  // 6 direct loads of 64 pairs per region
+static_assert(kRegChunks * 128 <= kRegPad, "region chunks fit the region's LDS");
 constexpr int kFdPrefetch = 3;                           // taps whose loads are in flight (one channel)
 // Several channels: one tap ahead.  The staging registers of three taps ahead
 // cost 3-channel blocks an occupancy step (143 -> 110 VGPRs with one tap);
@@ -60,6 +76,11 @@ constexpr int kFdPrefetch = 3;                           // taps whose loads are
 constexpr int kFdPrefetchMulti = 1;
 template <int NCH>
 constexpr int fd_prefetch() { return NCH == 1 ? kFdPrefetch : kFdPrefetchMulti; }
+// LDS regions: binary64 windows are copied straight into LDS by the loads (one
+// buffer per tap in flight, plus the one being read); the other arithmetics are
+// converted in registers and staged one tap ahead (two buffers).
+template <int PRE, int NCH>
+constexpr int fd_buffers() { return PRE == kPreF64 ? fd_prefetch<NCH>() + 1 : 2; }
 
 template <int PRE>
 __device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
@@ -70,52 +91,6 @@ __device__ __forceinline__ double gload(__amdgpu_buffer_rsrc_t r, uint32_t byte_
     const float2 f = __builtin_bit_cast(float2, v);
     return (double)f.x + (double)f.y;
 }
-
-// Abscissae (index q1 + 2 q2 + 4 q4) and ordinates (index q2 + 2 q3 + 4 q4) of the
-// sample positions n + tau - x_i of pixel (r, c), in window coordinates (Table 1:
-// x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 3.1 step (2)).
-template <typename R>
-struct PixGeom {
-    R a1, ap2, a3, ap4, cx, cy, wgt;   // wgt = 1 / (8 a1 a2 a3 a4): the ZP weights below are 8 x
-    __device__ __forceinline__ PixGeom(const Job &J, const Window &w, int64_t r, int64_t c)
-    {
-        const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
-        const R m = (R)J.inv_sqrt_m_d;
-        a1 = (R)af.x * m;
-        const R a2 = (R)af.y * m;
-        a3 = (R)af.z * m;
-        const R a4 = (R)af.w * m;
-        ap2 = a2 * (R)kRsqrt2;
-        ap4 = a4 * (R)kRsqrt2;
-        cx = (R)(c - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
-        cy = (R)(r - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
-        wgt = (R)1 / ((R)8 * a1 * a2 * a3 * a4);
-    }
-    __device__ __forceinline__ R x(int i) const
-    {
-        R v = cx;
-        if (i & 1) v -= a1;    // q1
-        if (i & 2) v -= ap2;   // q2
-        if (i & 4) v += ap4;   // q4
-        return v;
-    }
-    __device__ __forceinline__ R y(int i) const
-    {
-        R v = cy;
-        if (i & 1) v -= ap2;   // q2
-        if (i & 2) v -= a3;    // q3
-        if (i & 4) v -= ap4;   // q4
-        return v;
-    }
-};
-
-// Order of the 16 taps in the difference: four groups of fixed (q2, q4); inside a
-// group (q1, q3) = (0,0), (1,0), (1,1), (0,1), so a group needs two abscissae and two
-// ordinates.
-__host__ __device__ constexpr int step_q1(int k) { return (k & 3) == 1 || (k & 3) == 2; }
-__host__ __device__ constexpr int step_q2(int k) { return (k >> 2) & 1; }
-__host__ __device__ constexpr int step_q3(int k) { return (k & 3) >= 2; }
-__host__ __device__ constexpr int step_q4(int k) { return k >> 3; }
 
 // 8 x the seven ZP weights on the canonical triangle (see above) and the two
 // signed axis steps (oa along the larger remainder component, ob along the other).
@@ -160,92 +135,287 @@ struct ZpTap {
     }
 };
 
+// 8 x the ZP weights on the 3 x 3 lattice block around the nearest lattice point,
+// with no branch on the triangle: ZP is C1 and piecewise quadratic, its second
+// derivative jumps only across the two diagonals of the cell, so each weight is a
+// quadratic in d = (dx, dy) plus multiples of U = u|u| and V = v|v|, u = dx - dy,
+// v = dx + dy (one term per diagonal):
+//   (0, 0)   : 4 - 4 dx^2 - 4 dy^2          = 4 - 2 (|U| + |V|)
+//   (+-1, 0) : 1 +- 4 dx + 2 (dx^2 - dy^2) -+ (U + V)
+//   (0, +-1) : 1 +- 4 dy - 2 (dx^2 - dy^2) +- (U - V)
+//   (1, 1) : |V| + V    (-1, -1) : |V| - V    (1, -1) : |U| + U    (-1, 1) : |U| - U
+// ((i, j) = column offset i, row offset j; dx^2 - dy^2 = u v).  On each of the four
+// triangles they reduce to the seven quadratics listed above, and the two corners
+// away from the triangle get weight 0.
+// Nearest lattice point l (minus the origin o) and remainder d of a coordinate x.
+// binary64: x + 1.5 2^52 rounds x to an integer held in the low word (ties to even,
+// as rint), and subtracting the constant back gives round(x) exactly.
+__device__ __forceinline__ void nearest(double x, int o, int &l, double &d)
+{
+    constexpr double kMagic = 6755399441055744.0;   // 1.5 * 2^52
+    const double t = x + kMagic;
+    l = (int)(uint32_t)(unsigned long long)__double_as_longlong(t) - o;
+    d = x - (t - kMagic);
+}
+__device__ __forceinline__ void nearest(float x, int o, int &l, float &d)
+{
+    const float r = rintf(x);
+    l = (int)r - o;
+    d = x - r;
+}
+
+// One tap: sum over the 3 x 3 block of w * g, added to acc with the tap's sign.
+// g(r, c) reads the sample of block row r, column c (0..2).
+template <bool NEG, typename R, class G>
+__device__ __forceinline__ R zp_tap(R dx, R dy, const G &g, R acc)
+{
+    const R u = dx - dy, v = dx + dy;
+    const R U = u * fabs(u), V = v * fabs(v);
+    const R S = U + V, D = U - V;
+    const R A = fma((R)2, u * v, (R)1), B = (R)2 - A;   // 1 + 2 (dx^2 - dy^2), 1 - 2 (dx^2 - dy^2)
+    R w[9];
+    w[4] = fma((R)-2, fabs(U) + fabs(V), (R)4);   // (0, 0)
+    w[5] = fma((R)4, dx, A) - S;                  // (1, 0)
+    w[3] = fma((R)-4, dx, A) + S;                 // (-1, 0)
+    w[7] = fma((R)4, dy, B) + D;                  // (0, 1)
+    w[1] = fma((R)-4, dy, B) - D;                 // (0, -1)
+    w[8] = fabs(V) + V;                           // (1, 1)
+    w[0] = fabs(V) - V;                           // (-1, -1)
+    w[2] = fabs(U) + U;                           // (1, -1)
+    w[6] = fabs(U) - U;                           // (-1, 1)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc = fma(NEG ? -w[k] : w[k], (R)g(k / 3, k % 3), acc);
+    return acc;
+}
+
+// The same weights read from 7 samples: the centre, its 4 neighbours and, of each
+// diagonal pair of corners, the one on the side of the remainder (the other has
+// weight 0): (1, 1) if v >= 0 else (-1, -1), weight 2|V|; (1, -1) if u >= 0 else
+// (-1, 1), weight 2|U|.  base: byte offset of the block's corner (-1, -1); rs: bytes
+// per row.  g(off) reads the sample at byte offset off.
+template <bool NEG, typename R, class G>
+__device__ __forceinline__ R zp_tap7(R dx, R dy, const G &g, int base, int rs, R acc)
+{
+    const R u = dx - dy, v = dx + dy;
+    const R U = u * fabs(u), V = v * fabs(v);
+    const R S = U + V, D = U - V;
+    const R A = fma((R)2, u * v, (R)1), B = (R)2 - A;   // 1 + 2 (dx^2 - dy^2), 1 - 2 (dx^2 - dy^2)
+    const R w00 = fma((R)-2, fabs(U) + fabs(V), (R)4);
+    const R w10 = fma((R)4, dx, A) - S, wm0 = fma((R)-4, dx, A) + S;
+    const R w01 = fma((R)4, dy, B) + D, w0m = fma((R)-4, dy, B) - D;
+    const R wv = fabs(V) + fabs(V), wu = fabs(U) + fabs(U);
+    const int cv = base + (v >= (R)0 ? 2 * rs + 16 : 0);
+    const int cu = base + (u >= (R)0 ? 16 : 2 * rs);
+    const R s = NEG ? (R)-1 : (R)1;
+    acc = fma(s * w00, (R)g(base + rs + 8), acc);
+    acc = fma(s * w10, (R)g(base + rs + 16), acc);
+    acc = fma(s * wm0, (R)g(base + rs), acc);
+    acc = fma(s * w01, (R)g(base + 2 * rs + 8), acc);
+    acc = fma(s * w0m, (R)g(base + 8), acc);
+    acc = fma(s * wv, (R)g(cv), acc);
+    acc = fma(s * wu, (R)g(cu), acc);
+    return acc;
+}
+
+// Per-pass scales of pixel (r, c) and the pixel's state: invalid scales, or a
+// support beyond the window's reach (the same test, on the same binary32 scales,
+// as the scale map's overflow count) give a NaN output.
+template <typename R>
+struct PixScales {
+    R a1, ap2, a3, ap4, wgt;
+    bool bad;
+    __device__ __forceinline__ PixScales(const Job &J, int64_t r, int64_t c)
+    {
+        const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
+        const double d = ((double)af.y + (double)af.w) * kRsqrt2;
+        const float px = (float)(0.5 * ((double)af.x + d)) * 1.000001f;
+        const float py = (float)(0.5 * ((double)af.z + d)) * 1.000001f;
+        bad = !(af.x > 0.f && af.y > 0.f && af.z > 0.f && af.w > 0.f && isfinite(af.x + af.y + af.z + af.w)) ||
+              fmaxf(px, py) * J.inv_sqrt_m > (float)J.cap;
+        const R m = (R)J.inv_sqrt_m_d;
+        a1 = (R)af.x * m;
+        const R a2 = (R)af.y * m;
+        a3 = (R)af.z * m;
+        const R a4 = (R)af.w * m;
+        ap2 = a2 * (R)kRsqrt2;
+        ap4 = a4 * (R)kRsqrt2;
+        wgt = (R)1 / ((R)8 * a1 * a2 * a3 * a4);
+    }
+};
+
+// Order of the 16 taps in the difference: four groups of fixed (q2, q4); inside a
+// group (q1, q3) = (0,0), (1,0), (1,1), (0,1), so a group needs two abscissae and two
+// ordinates.  Abscissa index q1 + 2 q2 + 4 q4, ordinate index q2 + 2 q3 + 4 q4.
+__host__ __device__ constexpr int step_q1(int k) { return (k & 3) == 1 || (k & 3) == 2; }
+__host__ __device__ constexpr int step_q2(int k) { return (k >> 2) & 1; }
+__host__ __device__ constexpr int step_q3(int k) { return (k & 3) >= 2; }
+__host__ __device__ constexpr int step_q4(int k) { return k >> 3; }
+
+// Sample positions n + tau - x_i of pixel (r, c) in window coordinates (Table 1:
+// x_i = (q1 a1 + q2 a'2 - q4 a'4, q2 a'2 + q3 a3 + q4 a'4); tau: Sec. 3.1 step (2)),
+// abscissa / ordinate of group (q2, q4) with q1 = 0 / q3 = 0.
+template <typename R>
+__device__ __forceinline__ R grp_x(const PixScales<R> &P, R cx, int q2, int q4)
+{
+    R v = cx;
+    if (q2) v -= P.ap2;
+    if (q4) v += P.ap4;
+    return v;
+}
+template <typename R>
+__device__ __forceinline__ R grp_y(const PixScales<R> &P, R cy, int q2, int q4)
+{
+    R v = cy;
+    if (q2) v -= P.ap2;
+    if (q4) v -= P.ap4;
+    return v;
+}
+
 // Direct path for one pixel: every sample read from the window (for lanes whose
-// stencil left the staged region).  The tap coordinates are recomputed from the
-// scales one tap at a time (rolled loop), so that this path adds no registers to
-// the staged path above it.
+// stencil left the staged region).  The taps are formed one at a time (rolled
+// loop) so that this path adds no registers to the staged path.
 template <int PRE, int NCH, typename R>
-__device__ __forceinline__ void fd_direct(const Job &J, const Window &w, int64_t r, int64_t c,
+__device__ __forceinline__ void fd_direct(const Job &J, const Window &w, int64_t r, int64_t c, const PixScales<R> &P,
                                           const __amdgpu_buffer_rsrc_t (&rs)[NCH], R (&acc)[NCH])
 {
-    const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
-    const R m = (R)J.inv_sqrt_m_d;
-    const R a1 = (R)af.x * m, a2 = (R)af.y * m, a3 = (R)af.z * m, a4 = (R)af.w * m;
-    const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
-    const R cx = (R)(c - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
-    const R cy = (R)(r - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
+    const R cx = (R)(c - w.c0) + (R)0.5 * (P.a1 + P.ap2 - P.ap4 - (R)1);
+    const R cy = (R)(r - w.r0) + (R)0.5 * (P.ap2 + P.a3 + P.ap4 - (R)3);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[ch] = (R)0;
 #pragma unroll 1
     for (int i = 0; i < 16; ++i) {
         const int q1 = i & 1, q2 = (i >> 1) & 1, q3 = (i >> 2) & 1, q4 = (i >> 3) & 1;
-        R x = cx, y = cy;
-        if (q1) x -= a1;
-        if (q2) { x -= ap2; y -= ap2; }
-        if (q3) y -= a3;
-        if (q4) { x += ap4; y -= ap4; }
+        const R x = grp_x(P, cx, q2, q4) - (q1 ? P.a1 : (R)0);
+        const R y = grp_y(P, cy, q2, q4) - (q3 ? P.a3 : (R)0);
         const R rx = rint(x), ry = rint(y);
-        const ZpTap<R> z(x - rx, y - ry);
-        const int base = min(max((int)ry, 1), w.h - 2) * w.w + min(max((int)rx, 1), w.w - 2);
+        const R dx = x - rx, dy = y - ry;
+        const int base = (min(max((int)ry, 1), w.h - 2) - 1) * w.w + min(max((int)rx, 1), w.w - 2) - 1;
+        const bool neg = (q1 + q2 + q3 + q4) & 1;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const __amdgpu_buffer_rsrc_t rr = rs[ch];
-            const R F8 = z.apply([&](int off) { return gload<PRE>(rr, (uint32_t)off); }, base * 8, 8, w.w * 8);
-            acc[ch] = ((q1 + q2 + q3 + q4) & 1) ? acc[ch] - F8 : acc[ch] + F8;
+            auto g = [&](int rr_, int cc_) { return gload<PRE>(rr, (uint32_t)((base + rr_ * w.w + cc_) * 8)); };
+            acc[ch] = neg ? zp_tap<true>(dx, dy, g, acc[ch]) : zp_tap<false>(dx, dy, g, acc[ch]);
         }
     }
 }
 
-template <int PRE, int NCH, typename R>
-__device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH][kRegPad])
+// ---------------------------------------------------------------------------
+// Block plan (one thread per 16 x 16 block): the block's place in its tile, the
+// tile's window and the origins of the staged regions.  Region column = window
+// column - origin, chosen so that a pixel at block offset ox with the centre
+// pixel's scales lands on region column ox + 1 + kRegM.  Computed in binary64 from
+// the stored binary32 scales, as the difference does.
+// ---------------------------------------------------------------------------
+__device__ void fd_plan_block(const Job &J, int gb)
 {
-    // tile-major block order: all blocks of tile 0, then tile 1, ...
     const int bpt_x = J.T / kFdSide, bpt = bpt_x * bpt_x;
-    const int tile = lb / bpt, rem = lb - tile * bpt;
-    if (tile >= J.ntr * J.ntc) return;   // uniform
+    const int tile = gb / bpt, rem = gb - tile * bpt;
     const int by = rem / bpt_x, bx = rem - by * bpt_x;
     const int ti = tile / J.ntc, tj = tile - ti * J.ntc;
-    const int64_t br0 = (int64_t)ti * J.T + by * kFdSide, bc0 = (int64_t)tj * J.T + bx * kFdSide;
+    FdBlk B;
+    B.tile = tile;
+    B.br0 = ti * J.T + by * kFdSide;
+    B.bc0 = tj * J.T + bx * kFdSide;
+    B.pad = 0;
+    if (B.br0 >= J.H || B.bc0 >= J.W) {   // a block of a ragged tile that holds no pixel
+        B.wr0 = B.wc0 = B.ww = B.wh = 0;
+        for (int k = 0; k < 8; ++k) B.ax[k] = B.ay[k] = 0;
+        J.fdplan[gb] = B;
+        return;
+    }
+    const Window w = window_of(J, tile);
+    B.wr0 = (int32_t)w.r0;
+    B.wc0 = (int32_t)w.c0;
+    B.ww = w.w;
+    B.wh = w.h;
+    const int64_t ra = min((int64_t)B.br0 + kFdSide / 2, J.H - 1), ca = min((int64_t)B.bc0 + kFdSide / 2, J.W - 1);
+    const float4 af = *reinterpret_cast<const float4 *>(J.scales + ra * J.sc_rs + ca * 4);
+    const double m = J.inv_sqrt_m_d;
+    const double a1 = (double)af.x * m, a3 = (double)af.z * m;
+    const double ap2 = (double)af.y * m * kRsqrt2, ap4 = (double)af.w * m * kRsqrt2;
+    const double cx = (double)(ca - w.c0) + 0.5 * (a1 + ap2 - ap4 - 1.0);
+    const double cy = (double)(ra - w.r0) + 0.5 * (ap2 + a3 + ap4 - 3.0);
+    for (int k = 0; k < 8; ++k) {
+        const int b0 = k & 1, b1 = (k >> 1) & 1, b2 = (k >> 2) & 1;
+        // abscissa k = q1 + 2 q2 + 4 q4; ordinate k = q2 + 2 q3 + 4 q4 (Table 1, tau)
+        const double x = cx - (b0 ? a1 : 0.0) - (b1 ? ap2 : 0.0) + (b2 ? ap4 : 0.0);
+        const double y = cy - (b0 ? ap2 : 0.0) - (b1 ? a3 : 0.0) - (b2 ? ap4 : 0.0);
+        int ix = (int)rint(x), iy = (int)rint(y);
+        if (!(ix >= 1)) ix = 1;   // also a NaN scale: any origin in the window
+        if (!(iy >= 1)) iy = 1;
+        ix = min(ix, w.w - 2);
+        iy = min(iy, w.h - 2);
+        B.ax[k] = ix - (int)(ca - B.bc0) - 1 - kRegM;
+        B.ay[k] = iy - (int)(ra - B.br0) - 1 - kRegM;
+    }
+    J.fdplan[gb] = B;
+}
+
+__global__ __launch_bounds__(256) void k_fd_plan(Job J, int nblocks)
+{
+    const int lb = blockIdx.x * blockDim.x + threadIdx.x;
+    const int bpt = (J.T / kFdSide) * (J.T / kFdSide);
+    if (lb < nblocks) fd_plan_block(J, J.tr0 * J.ntc * bpt + lb);
+}
+
+// one thread per block of any image of the table (blk_base: the job's first block)
+__global__ __launch_bounds__(256) void k_fd_plan_batch(const Job *jobs, int n, int total)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= total) return;
+    const int j = find_job(jobs, n, b, 1);
+    fd_plan_block(jobs[j], b - jobs[j].blk_base);
+}
+
+// 16 bytes per lane from a buffer straight into LDS: lane l writes dst + 16 l
+// (dst uniform).  The host pass of the compiler has no LDS address space.
+__device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t r, double *dst, uint32_t byte_off)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)dst, 16, byte_off, 0, 0, 0);
+#else
+    (void)r, (void)dst, (void)byte_off;
+#endif
+}
+
+// vmcnt wait with the other counters left alone (gfx9 s_waitcnt encoding)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int PRE, int NCH, typename R>
+__device__ __forceinline__ void fd_block(const Job &J, int gb, double (*lds)[NCH][kRegPad])
+{
+    constexpr int PF = fd_prefetch<NCH>();
+    constexpr int NB = fd_buffers<PRE, NCH>();
+    constexpr bool kDirect = PRE == kPreF64;   // loads write the regions in LDS themselves
+    const FdBlk &B = J.fdplan[gb];
+    const int64_t br0 = B.br0, bc0 = B.bc0;
     if (br0 >= J.H || bc0 >= J.W) return;   // uniform: block entirely outside a ragged tile
-    const int t = threadIdx.x;
+    const int tile = B.tile;
+    const int t = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
     const int64_t r = br0 + t / kFdSide, c = bc0 + t % kFdSide;
     const bool live = r < J.H && c < J.W;
-    const Window w = window_of(J, tile);
+    Window w;
+    w.r0 = B.wr0;
+    w.c0 = B.wc0;
+    w.w = B.ww;
+    w.h = B.wh;
     const int ww = w.w;
-    // Region origins, one per distinct abscissa / ordinate, from the block's centre
-    // pixel: region column = window column - AX, so that a pixel at block offset ox
-    // with the centre's scales lands on column ox + 1 + kRegM.  Lane k < 16 of each
-    // wave computes the centre's coordinate k (abscissa k, or ordinate k - 8) and the
-    // values are read back as uniform registers.
     int AX[8], AY[8];
-    {
-        const int64_t ra = min(br0 + kFdSide / 2, J.H - 1), ca = min(bc0 + kFdSide / 2, J.W - 1);
-        const float4 af = *reinterpret_cast<const float4 *>(J.scales + ra * J.sc_rs + ca * 4);
-        const R m = (R)J.inv_sqrt_m_d;
-        const R a1 = (R)af.x * m, a2 = (R)af.y * m, a3 = (R)af.z * m, a4 = (R)af.w * m;
-        const R ap2 = a2 * (R)kRsqrt2, ap4 = a4 * (R)kRsqrt2;
-        const int k = t & 15, b0 = k & 1, b1 = (k >> 1) & 1, b2 = (k >> 2) & 1;
-        R v;
-        if (k < 8) {   // same operations as PixGeom::x / PixGeom::y
-            v = (R)(ca - w.c0) + (R)0.5 * (a1 + ap2 - ap4 - (R)1);
-            if (b0) v -= a1;
-            if (b1) v -= ap2;
-            if (b2) v += ap4;
-        } else {
-            v = (R)(ra - w.r0) + (R)0.5 * (ap2 + a3 + ap4 - (R)3);
-            if (b0) v -= ap2;
-            if (b1) v -= a3;
-            if (b2) v -= ap4;
-        }
-        const int iv = min(max((int)rint(v), 1), (k < 8 ? ww : w.h) - 2);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            AX[i] = __builtin_amdgcn_readlane(iv, i) - (int)(ca - bc0) - 1 - kRegM;
-            AY[i] = __builtin_amdgcn_readlane(iv, 8 + i) - (int)(ra - br0) - 1 - kRegM;
-        }
+    for (int k = 0; k < 8; ++k) {
+        AX[k] = __builtin_amdgcn_readfirstlane(B.ax[k]);
+        AY[k] = __builtin_amdgcn_readfirstlane(B.ay[k]);
     }
-    const PixGeom<R> G(J, w, live ? r : br0, live ? c : bc0);
-    R wgt = G.wgt;
+    const PixScales<R> P(J, live ? r : br0, live ? c : bc0);
+    const R cx = (R)((live ? c : bc0) - w.c0) + (R)0.5 * (P.a1 + P.ap2 - P.ap4 - (R)1);
+    const R cy = (R)((live ? r : br0) - w.r0) + (R)0.5 * (P.ap2 + P.a3 + P.ap4 - (R)3);
+    R wgt = P.wgt;
     if (PRE == kPreI64) wgt *= (R)2;
     const unsigned char *gbase = static_cast<const unsigned char *>(J.g);
     const int slot_bytes = (int)(J.slot_elems * 8);
@@ -255,94 +425,140 @@ __device__ __forceinline__ void fd_block(const Job &J, int lb, double (*lds)[NCH
         rs[ch] = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<unsigned char *>(gbase + ((int64_t)tile * J.C + ch) * J.slot_elems * 8), 0, slot_bytes,
             kBufWord3);
-    // loads of tap j go to register slot j % PF; tap j is fetched PF taps before it
-    // is staged
-    // Region entry e = t + 256 k of tap i is window sample (AY + e / 27) * ww + AX + e % 27:
-    // a fixed per-thread part and a uniform per-tap part.  Entries past kRegN are
-    // loaded and staged but never read.
-    int toff[kRegLoads];
+    // Region of tap i: region row y, column x (x < kRS) is window sample
+    // (AY + y) * ww + AX + x, a uniform per-tap part plus a fixed per-thread part.
+    //  - direct loads: chunk k of 64 pairs of columns; wave w loads chunks w and w + 4
+    //    (if < kRegChunks), its lane l the pair p = 64 k + l;
+    //  - register staging: entry e = t + 256 k.
+    // Entries past the region's rows are loaded and stored but never read.
+    constexpr int NL = kDirect ? 2 : kRegLoads;
+    int toff[NL];
 #pragma unroll
-    for (int k = 0; k < kRegLoads; ++k) {
-        const int e = t + 256 * k;
-        toff[k] = (e / kRegS) * ww + e % kRegS;
+    for (int k = 0; k < NL; ++k) {
+        if (kDirect) {
+            const int pr = 64 * (wave + 4 * k) + lane;
+            toff[k] = (pr / (kRS / 2)) * ww + 2 * (pr % (kRS / 2));
+        } else {
+            const int e = t + 256 * k;
+            toff[k] = (e / kRS) * ww + e % kRS;
+        }
     }
-    constexpr int PF = fd_prefetch<NCH>();
-    double pre[PF][NCH][kRegLoads];
+    const bool two_chunks = wave + 4 < kRegChunks;   // uniform
+    double pre[kDirect ? 1 : PF][NCH][kRegLoads];
     auto fetch = [&](int i) {   // region of the tap processed at step i
         const int xi = step_q1(i) + 2 * step_q2(i) + 4 * step_q4(i);
         const int yi = step_q2(i) + 2 * step_q3(i) + 4 * step_q4(i);
         const int sb = AY[yi] * ww + AX[xi];   // uniform
+        if constexpr (kDirect) {
 #pragma unroll
-        for (int k = 0; k < kRegLoads; ++k) {
-            const uint32_t off = (uint32_t)(sb + toff[k]) * 8u;   // negative wraps: OOB -> 0
+            for (int k = 0; k < 2; ++k) {
+                if (k == 1 && !two_chunks) break;
+                const uint32_t off = (uint32_t)(sb + toff[k]) * 8u;   // negative wraps: OOB -> 0
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) pre[i % PF][ch][k] = gload<PRE>(rs[ch], off);
+                for (int ch = 0; ch < NCH; ++ch) lds_load16(rs[ch], &lds[i % NB][ch][128 * (wave + 4 * k)], off);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kRegLoads; ++k) {
+                const uint32_t off = (uint32_t)(sb + toff[k]) * 8u;   // negative wraps: OOB -> 0
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) pre[i % PF][ch][k] = gload<PRE>(rs[ch], off);
+            }
         }
     };
     auto stage = [&](int i) {
+        if constexpr (!kDirect) {
 #pragma unroll
-        for (int k = 0; k < kRegLoads; ++k) {
+            for (int k = 0; k < kRegLoads; ++k) {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) lds[i & 1][ch][t + 256 * k] = pre[i % PF][ch][k];
+                for (int ch = 0; ch < NCH; ++ch) lds[i & 1][ch][t + 256 * k] = pre[i % PF][ch][k];
+            }
         }
+    };
+    // direct loads: before reading the region of tap i, wait until this wave's loads
+    // of tap i have landed (the loads of the later taps already issued may still run)
+    auto wait_tap = [&](auto later) {
+        constexpr int n = decltype(later)::value;
+        if (two_chunks) wait_vmcnt<2 * n * NCH>();
+        else wait_vmcnt<n * NCH>();
     };
     R acc[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[ch] = (R)0;
     bool outside = false;   // some stencil of this lane left its staged region
+    if constexpr (kDirect) {
 #pragma unroll
-    for (int j = 0; j < PF; ++j) fetch(j);
-    stage(0);
-    lds_barrier();
-    R gdx[2], gdy[2];   // remainders of the current group's abscissae / ordinates
-    int glx[2], gly[2];  // their region offsets (gly in samples of whole rows)
+        for (int j = 0; j < PF; ++j) fetch(j);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (i + PF < 16) fetch(i + PF);
+        for (int j = 0; j < PF; ++j) fetch(j);
+        stage(0);
+        lds_barrier();
+    }
+    R GDX[2], GDY[2];      // remainders of the current group's abscissae / ordinates
+    int GOX[2], GOY[2];    // byte offsets of their stencils' first column / row in the region
+    auto step = [&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (kDirect) {
+            // every wave's loads of tap i are in LDS; tap i - 1 is read by all.  No
+            // release fence: it would wait for the later taps' loads as well
+            wait_tap(std::integral_constant<int, (i + PF - 1 < 16 ? PF - 1 : 15 - i)>{});
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            if (i + PF < 16) fetch(i + PF);
+        } else {
+            if (i + PF < 16) fetch(i + PF);
+        }
         const int q1 = step_q1(i), q2 = step_q2(i), q3 = step_q3(i), q4 = step_q4(i);
         if ((i & 3) == 0) {
+            const R xg = grp_x(P, cx, q2, q4), yg = grp_y(P, cy, q2, q4);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int xi = u + 2 * q2 + 4 * q4, yi = q2 + 2 * u + 4 * q4;
-                const R x = G.x(xi), y = G.y(yi);
-                const R rx = rint(x), ry = rint(y);
-                gdx[u] = x - rx;
-                gdy[u] = y - ry;
-                // position in the region (clamped; a lane whose stencil leaves it is redone below)
-                const int lx = min(max((int)rx, 1), ww - 2) - AX[xi], ly = min(max((int)ry, 1), w.h - 2) - AY[yi];
-                outside |= (unsigned)(lx - 1) > (unsigned)(kRegS - 3) || (unsigned)(ly - 1) > (unsigned)(kRegS - 3);
-                glx[u] = min(max(lx, 1), kRegS - 2);
-                gly[u] = min(max(ly, 1), kRegS - 2) * kRegS;
+                int lx, ly;
+                nearest(u ? xg - P.a1 : xg, AX[xi], lx, GDX[u]);
+                nearest(u ? yg - P.a3 : yg, AY[yi], ly, GDY[u]);
+                // stencil inside the region: nearest point in [1, kRegS - 2]
+                const int cxl = min(max(lx, 1), kRegS - 2), cyl = min(max(ly, 1), kRegS - 2);
+                outside |= (cxl != lx) | (cyl != ly);
+                GOX[u] = (cxl - 1) * 8;
+                GOY[u] = (cyl - 1) * (kRS * 8);
             }
         }
-        const ZpTap<R> z(gdx[q1], gdy[q3]);
-        const int base = (gly[q3] + glx[q1]) * 8;
+        const int base = GOY[q3] + GOX[q1];
+        const bool neg = (q1 + q2 + q3 + q4) & 1;   // w_i = (-1)^(q1+..+q4) w
+        const int buf = kDirect ? i % NB : (i & 1);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const unsigned char *L = reinterpret_cast<const unsigned char *>(lds[i & 1][ch]);
-            const R F8 = z.apply([&](int off) { return *reinterpret_cast<const double *>(L + off); }, base, 8, kRegS * 8);
-            acc[ch] = ((q1 + q2 + q3 + q4) & 1) ? acc[ch] - F8 : acc[ch] + F8;   // w_i = (-1)^(q1+..+q4) w
+            const unsigned char *L0 = reinterpret_cast<const unsigned char *>(lds[buf][ch]);
+            auto g = [&](int off) { return *reinterpret_cast<const double *>(L0 + off); };
+            acc[ch] = neg ? zp_tap7<true>(GDX[q1], GDY[q3], g, base, kRS * 8, acc[ch])
+                          : zp_tap7<false>(GDX[q1], GDY[q3], g, base, kRS * 8, acc[ch]);
             // keep this tap's arithmetic here: otherwise it is sunk into the final store
             // block and every tap's samples stay live in registers until then
             __asm__ volatile("" : "+v"(acc[ch]));
         }
-        if (i + 1 < 16) {
-            stage(i + 1);
-            lds_barrier();
+        if constexpr (!kDirect) {
+            if (i + 1 < 16) {
+                stage(i + 1);
+                lds_barrier();
+            }
         }
-    }
-    if (live && outside) fd_direct<PRE, NCH, R>(J, w, r, c, rs, acc);
+    };
+    [&]<int... I>(std::integer_sequence<int, I...>) { (step(std::integral_constant<int, I>{}), ...); }(
+        std::make_integer_sequence<int, 16>{});
+    if (live && outside && !P.bad) fd_direct<PRE, NCH, R>(J, w, r, c, P, rs, acc);
     if (live) {
         float *o = J.out + r * J.out_rs + c * J.C;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) o[ch] = (float)(acc[ch] * wgt);
+        for (int ch = 0; ch < NCH; ++ch) o[ch] = P.bad ? __builtin_nanf("") : (float)(acc[ch] * wgt);
     }
 }
 
 template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
 {
-    __shared__ double lds[2][NCH][kRegPad];
+    __shared__ double lds[fd_buffers<PRE, NCH>()][NCH][kRegPad];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bpt = (J.T / kFdSide) * (J.T / kFdSide);
     if (lb < nblocks) fd_block<PRE, NCH, R>(J, J.tr0 * J.ntc * bpt + lb, lds);
@@ -352,7 +568,7 @@ __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
 template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) void k_fd_batch(const Job *jobs, int n, int total)
 {
-    __shared__ double lds[2][NCH][kRegPad];
+    __shared__ double lds[fd_buffers<PRE, NCH>()][NCH][kRegPad];
     const int b = blockIdx.x;
     if (b >= total) return;
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 1));
@@ -533,6 +749,21 @@ hipError_t launch_fd_uniform(const Job &j, const double *a, hipStream_t s)
     case kPreF32C: hipLaunchKernelGGL((k_fd_uniform<kPreF32C, 3>), dim3(grid), dim3(256), bytes, s, j, nb, cap); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_plan(const Job &j, hipStream_t s)
+{
+    const int nb = (j.tr1 - j.tr0) * j.ntc * (j.T / kFdSide) * (j.T / kFdSide);
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fd_plan, dim3((nb + 255) / 256), dim3(256), 0, s, j, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_plan_batch(const Job *jobs, int n, int total_blocks, hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fd_plan_batch, dim3((total_blocks + 255) / 256), dim3(256), 0, s, jobs, n, total_blocks);
     return hipGetLastError();
 }
 

@@ -29,6 +29,20 @@ struct TileStat {
 };
 static_assert(sizeof(TileStat) == 32, "TileStat layout");
 
+// Per 16 x 16 pixel block of the finite difference: the block's window and the
+// origins of its staged sample regions, one per distinct abscissa / ordinate of the
+// 16 taps (from the block's centre pixel), in window coordinates.  Written once per
+// filter call after the scale map (k_fd_plan) and read by every pass, whose scales
+// are the filter's times 1 / sqrt(order).
+struct FdBlk {
+    int32_t ax[8], ay[8];    // region origins: abscissa k = q1 + 2 q2 + 4 q4, ordinate k = q2 + 2 q3 + 4 q4
+    int32_t wr0, wc0;        // window origin (image rows / columns)
+    int32_t ww, wh;          // window width / height
+    int32_t br0, bc0;        // first pixel of the block
+    int32_t tile, pad;
+};
+static_assert(sizeof(FdBlk) == 96, "FdBlk layout");
+
 // One image of a filter call, for one pass.  Passed by value for a single image
 // and stored in a device table for batched launches.
 struct Job {
@@ -65,6 +79,11 @@ struct Job {
     int32_t boundary;        // Boundary: what a pass reads outside the image
     // single-image launches cover the tile rows [tr0, tr1) (scale map: their pixel rows)
     int32_t tr0, tr1;
+    // finite-difference block plan (k_fd_plan writes it, k_fd reads it): one FdBlk
+    // per block of the tile-major block list
+    FdBlk *fdplan;
+    // serving: the request's invalid / overflow pixel counts (nullptr: not kept)
+    uint32_t *req_counts;
     // look-up-table scale map (nullptr: the solve per pixel)
     const float *lut;        // lut_n x lut_n float4, [i][j]: rho = (n-1)/i, phi = j pi / (4 (n-1)), s = 1
     int32_t lut_n, pad2;
@@ -122,6 +141,9 @@ hipError_t launch_scale_map(const Job &j, hipStream_t s);
 hipError_t launch_lut_build(float *lut, int n, double eps, hipStream_t s);
 hipError_t launch_preint(const Job &j, hipStream_t s);
 hipError_t launch_fd(const Job &j, hipStream_t s);
+// the finite difference's block plan (after the scale map, before the first pass)
+hipError_t launch_fd_plan(const Job &j, hipStream_t s);
+hipError_t launch_fd_plan_batch(const Job *jobs, int n, int total_blocks, hipStream_t s);
 // constant filter (every pixel's scales equal; 3 channels, binary64 difference):
 // whether the staged region of a block fits, and the launch
 bool fd_uniform_fits(double a1, double a2, double a3, double a4, int channels);

@@ -394,6 +394,10 @@ __device__ void scale_map_block(const Job &J, int lb)
         if (n[1]) atomicAdd(&ts->eps_active, n[1]);
         if (n[2]) atomicAdd(&ts->invalid, n[2]);
         if (n[3]) atomicAdd(&ts->overflow, n[3]);
+        if (J.req_counts) {
+            if (n[2]) atomicAdd(&J.req_counts[0], n[2]);
+            if (n[3]) atomicAdd(&J.req_counts[1], n[3]);
+        }
     }
     __syncthreads();   // the shared records are reused by the next block of a persistent loop
 }

@@ -135,7 +135,8 @@ Plan plan_for(const svf_image *in, int order, const svf_opts *o)
     p.slot = slot_elems_for(p.T, p.cap);
     p.off_tstat = 0;
     p.off_scales = align_up((size_t)p.ntr * p.ntc * sizeof(TileStat), 256);
-    p.off_g = align_up(p.off_scales + (size_t)in->H * in->W * 4 * sizeof(float), 256);
+    p.off_fdplan = align_up(p.off_scales + (size_t)in->H * in->W * 4 * sizeof(float), 256);
+    p.off_g = align_up(p.off_fdplan + (size_t)p.ntr * p.ntc * (p.T / 16) * (p.T / 16) * sizeof(FdBlk), 256);
     // second pass buffer: pass outputs alternate between it and the caller's output
     p.off_tmp = align_up(p.off_g + (size_t)p.ntr * p.ntc * in->channels * p.slot * 8, 256);
     p.bytes = p.off_tmp + (order > 1 ? (size_t)in->H * in->W * in->channels * sizeof(float) : 0);
@@ -212,7 +213,7 @@ svf_status ensure_bands(svf_ctx *ctx, int nb, int order)
         hipError_t e = hipStreamCreateWithFlags(&ctx->band_stream[b], hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamCreateWithFlags");
     }
-    const size_t need = 1 + (size_t)order * svf_ctx::kMaxBands;
+    const size_t need = 1 + (size_t)(order + 1) * svf_ctx::kMaxBands;   // fork, passes, pass-0 sums
     while (ctx->band_events.size() < need) {
         hipEvent_t ev;
         hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -244,6 +245,7 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
         j.sc_rs = in->W * 4;
     }
     j.tstat = reinterpret_cast<TileStat *>(ws + p.off_tstat);
+    j.fdplan = reinterpret_cast<FdBlk *>(ws + p.off_fdplan);
     j.g = ws + p.off_g;
     j.slot_elems = p.slot;
     j.T = p.T;
@@ -540,6 +542,8 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
     if (nb <= 1) {
         e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(pass_job(0, 0, p.ntr), stream); });
         if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+        e = launch_fd_plan(pass_job(0, 0, p.ntr), stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "block plan launch");
         for (int pass = 0; pass < order; ++pass) {
             const Job jp = pass_job(pass, 0, p.ntr);
             e = timed_launch(ctx, kClsPreint, stream, [&] { return launch_preint(jp, stream); });
@@ -566,19 +570,43 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
             hipStream_t sb = ctx->band_stream[b];
             e = timed_launch(ctx, kClsScaleMap, sb, [&] { return launch_scale_map(pass_job(0, tr[b], tr[b + 1]), sb); });
             if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+            e = launch_fd_plan(pass_job(0, tr[b], tr[b + 1]), sb);
+            if (e != hipSuccess) return hip_fail(ctx, e, "block plan launch");
         }
+        // rows of the pass input that band b's windows read (beyond the band: the halo,
+        // and under the replicate and mirror rules the rows a border reflects)
+        auto reach = [&](int b, int64_t &lo, int64_t &hi) {
+            lo = (int64_t)tr[b] * p.T - halo;
+            hi = (int64_t)tr[b + 1] * p.T + halo;
+            if (o.boundary != SVF_BOUNDARY_ZERO) {
+                const int64_t H = in->H, lo0 = lo;
+                if (hi > H) lo = std::min(lo, std::max<int64_t>(0, 2 * H - hi));
+                if (lo0 < 0) hi = std::max(hi, std::min<int64_t>(H, -lo0));
+            }
+        };
+        // whether band a's windows read rows of band b
+        auto reads = [&](int a, int b) {
+            int64_t lo, hi;
+            reach(a, lo, hi);
+            return a != b && (int64_t)tr[b + 1] * p.T > lo && (int64_t)tr[b] * p.T < hi;
+        };
+        // An output that overlaps the input in memory, written by pass 0: a band's
+        // difference must not overwrite input rows that another band's
+        // pre-integration has still to read.
+        auto span = [](const svf_image *im) {
+            const size_t esz = im->dtype == SVF_U16 ? 2 : 4;
+            const uintptr_t a = reinterpret_cast<uintptr_t>(im->data);
+            return std::make_pair(a, a + ((size_t)(im->H - 1) * im->row_stride + (size_t)im->W * im->channels) * esz);
+        };
+        const auto si = span(in), so = span(out);
+        const bool aliased_pass0 = si.first < so.second && so.first < si.second && pass_out(0) == out->data;
+        auto ev_pre = [&](int b) { return ctx->band_events[1 + order * svf_ctx::kMaxBands + b]; };
         for (int pass = 0; pass < order; ++pass) {
             for (int b = 0; b < nb; ++b) {
                 hipStream_t sb = ctx->band_stream[b];
                 if (pass > 0) {
-                    int64_t lo = (int64_t)tr[b] * p.T - halo, hi = (int64_t)tr[b + 1] * p.T + halo;
-                    if (o.boundary != SVF_BOUNDARY_ZERO) {
-                        const int64_t H = in->H, lo0 = lo;
-                        if (hi > H) lo = std::min(lo, std::max<int64_t>(0, 2 * H - hi));
-                        if (lo0 < 0) hi = std::max(hi, std::min<int64_t>(H, -lo0));
-                    }
                     for (int o2 = 0; o2 < nb; ++o2) {
-                        if (o2 == b || (int64_t)tr[o2 + 1] * p.T <= lo || (int64_t)tr[o2] * p.T >= hi) continue;
+                        if (!reads(b, o2)) continue;
                         e = hipStreamWaitEvent(sb, ev(pass - 1, o2), 0);
                         if (e != hipSuccess) return hip_fail(ctx, e, "band dependency");
                     }
@@ -586,10 +614,30 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
                 const Job jp = pass_job(pass, tr[b], tr[b + 1]);
                 e = timed_launch(ctx, kClsPreint, sb, [&] { return launch_preint(jp, sb); });
                 if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
+                if (pass == 0 && aliased_pass0) {   // the difference follows once every reader is done
+                    e = hipEventRecord(ev_pre(b), sb);
+                    if (e != hipSuccess) return hip_fail(ctx, e, "band event");
+                    continue;
+                }
                 e = timed_launch(ctx, kClsFd, sb, [&] { return launch_fd(jp, sb); });
                 if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
                 e = hipEventRecord(ev(pass, b), sb);
                 if (e != hipSuccess) return hip_fail(ctx, e, "band event");
+            }
+            if (pass == 0 && aliased_pass0) {
+                for (int b = 0; b < nb; ++b) {
+                    hipStream_t sb = ctx->band_stream[b];
+                    for (int o2 = 0; o2 < nb; ++o2) {
+                        if (!reads(o2, b)) continue;
+                        e = hipStreamWaitEvent(sb, ev_pre(o2), 0);
+                        if (e != hipSuccess) return hip_fail(ctx, e, "band dependency");
+                    }
+                    const Job jp = pass_job(0, tr[b], tr[b + 1]);
+                    e = timed_launch(ctx, kClsFd, sb, [&] { return launch_fd(jp, sb); });
+                    if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
+                    e = hipEventRecord(ev(0, b), sb);
+                    if (e != hipSuccess) return hip_fail(ctx, e, "band event");
+                }
             }
         }
         for (int b = 0; b < nb; ++b) {   // join: the caller's stream waits for every band

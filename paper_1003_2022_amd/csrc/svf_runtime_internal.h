@@ -49,7 +49,7 @@ namespace svf {
 struct Plan {
     int T = 0, cap = 0, ntr = 0, ntc = 0;
     int64_t slot = 0;
-    size_t off_tstat = 0, off_scales = 0, off_g = 0, off_tmp = 0, bytes = 0;
+    size_t off_tstat = 0, off_scales = 0, off_fdplan = 0, off_g = 0, off_tmp = 0, bytes = 0;
 };
 
 svf_status fail(svf_ctx *ctx, svf_status st, const char *fmt, ...);

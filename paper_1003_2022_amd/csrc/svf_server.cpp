@@ -96,6 +96,7 @@ struct Req {
     Plan plan;
     size_t bytes = 0, off = 0;
     int pass = -1;                 // next pass to run; -1: not admitted
+    int slot = -1;                 // counter slot while admitted (invalid / overflow pixels)
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = SVF_EBUSY;
     bool done = false;
@@ -108,6 +109,7 @@ struct Req {
 
 struct StepBuf {
     Job *d = nullptr, *h = nullptr;
+    uint32_t *h_counts = nullptr;      // pinned copy of the counter slots after this step
     hipEvent_t ev = nullptr;
     bool pending = false;
     std::vector<uint64_t> finishing;   // requests whose last pass runs in this step
@@ -135,13 +137,17 @@ struct Server {
     double busy_since = -1;
     std::string err;
     float *lut = nullptr;              // the server's own scale table (SVF_SCALE_LUT)
+    uint32_t *d_counts = nullptr;      // per slot: invalid and overflow pixels of the request holding it
+    std::vector<int> free_slots;
+    std::deque<uint64_t> finished;     // finished requests, oldest first (their state stays readable)
+    size_t keep_finished = 0;
 };
 
 Server *srv(svf_ctx *ctx) { return static_cast<Server *>(ctx->server); }
 
 // Launch one step from the tables in `b`; returns false on a HIP error.
-bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *counts, const int *tot_tiles,
-                 const int *tot_blk)
+bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, int tot_plan, const int *counts,
+                 const int *tot_tiles, const int *tot_blk)
 {
     hipError_t e = hipMemcpyAsync(b.d, b.h, sizeof(Job) * kTables * S->cap, hipMemcpyHostToDevice, S->stream);
     if (e != hipSuccess) return false;
@@ -150,14 +156,18 @@ bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, const int *coun
         const Job &j = b.h[i];
         e = launch_fill_u32(reinterpret_cast<uint32_t *>(j.tstat), 0u,
                             (int64_t)j.ntr * j.ntc * (int64_t)(sizeof(TileStat) / 4), S->stream);
+        if (e == hipSuccess) e = launch_fill_u32(j.req_counts, 0u, 2, S->stream);
     }
     if (e == hipSuccess && nsmap) e = launch_scale_map_batch(b.d, nsmap, tot_smap, kPersistentScale, S->lut != nullptr, S->stream);
+    if (e == hipSuccess && nsmap) e = launch_fd_plan_batch(b.d, nsmap, tot_plan, S->stream);
     for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
         if (counts[ch]) e = launch_preint_batch(b.d + ch * S->cap, counts[ch], tot_tiles[ch], kPersistentPreint,
                                                 S->cfg.opts.preint, S->stream);
     for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
         if (counts[ch]) e = launch_fd_batch(b.d + ch * S->cap, counts[ch], tot_blk[ch], kPersistentFd,
                                             S->cfg.opts.preint, S->cfg.opts.fd_fp32, ch, S->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.h_counts, S->d_counts, sizeof(uint32_t) * 2 * S->cap, hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess) e = hipEventRecord(b.ev, S->stream);
     return e == hipSuccess;
 }
@@ -171,6 +181,25 @@ void note_idle(Server *S, double t)
     }
 }
 
+// A request reached its final state (called under S->mu): remember it, and forget
+// the oldest finished requests beyond the retention count.
+void note_finished(Server *S, uint64_t id)
+{
+    S->finished.push_back(id);
+    while (S->finished.size() > S->keep_finished) {
+        S->reqs.erase(S->finished.front());
+        S->finished.pop_front();
+    }
+}
+
+// Give an admitted request's arena range and counter slot back (called under S->mu).
+void release(Server *S, Req &q)
+{
+    S->arena.release(q.off, q.bytes);
+    if (q.slot >= 0) S->free_slots.push_back(q.slot);
+    q.slot = -1;
+}
+
 // End an admitted request that was cancelled and has no step on the device
 // (called under S->mu): its region goes back to the arena.
 void end_cancelled(Server *S, uint64_t id, Req &q, double t)
@@ -178,10 +207,11 @@ void end_cancelled(Server *S, uint64_t id, Req &q, double t)
     q.done = true;
     q.status = SVF_ECANCELLED;
     q.t_done = t;
-    S->arena.release(q.off, q.bytes);
+    release(S, q);
     S->stats.cancelled++;
     S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), id));
     note_idle(S, t);
+    note_finished(S, id);
 }
 
 // Host side of a finished step: complete its finishing requests.
@@ -194,12 +224,16 @@ void retire(Server *S, StepBuf &b)
     for (uint64_t id : b.finishing) {
         Req &q = S->reqs[id];
         q.done = true;
-        q.status = e == hipSuccess ? SVF_OK : SVF_EHIP;
+        // pixels with an invalid field entry or a support beyond max_reach_px (their
+        // outputs are NaN or the smallest filter) fail the request as svf_filter's report does
+        const uint32_t inv = b.h_counts[2 * q.slot], ovf = b.h_counts[2 * q.slot + 1];
+        q.status = e != hipSuccess ? SVF_EHIP : inv ? SVF_EINVAL : ovf ? SVF_ERANGE : SVF_OK;
         q.t_done = t;
-        S->arena.release(q.off, q.bytes);
+        release(S, q);
         S->stats.completed++;
         S->stats.pixels += q.r.out.H * q.r.out.W * q.r.out.channels;
         S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), id));
+        note_finished(S, id);
     }
     for (uint64_t id : b.running) {
         Req &q = S->reqs[id];
@@ -227,8 +261,10 @@ void loop(Server *S)
             while (!S->queue.empty() && (int)S->inflight.size() < S->cfg.max_inflight) {
                 Req &q = S->reqs[S->queue.front()];
                 size_t off;
-                if (!S->arena.alloc(q.bytes, off)) break;
+                if (S->free_slots.empty() || !S->arena.alloc(q.bytes, off)) break;
                 q.off = off;
+                q.slot = S->free_slots.back();
+                S->free_slots.pop_back();
                 q.pass = 0;
                 q.t_admit = now_us();
                 S->inflight.push_back(S->queue.front());
@@ -262,7 +298,7 @@ void loop(Server *S)
         }
         // ---- build the tables (only this thread writes q.pass / q.off) ----
         int counts[kTables] = {}, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
-        int tot_smap = 0;
+        int tot_smap = 0, tot_plan = 0;
         int nsmap = 0;
         for (auto &pr : running) {
             const uint64_t id = pr.first;
@@ -271,6 +307,7 @@ void loop(Server *S)
             Plan pp = p;
             pp.off_tstat = q.off + p.off_tstat;
             pp.off_scales = q.off + p.off_scales;
+            pp.off_fdplan = q.off + p.off_fdplan;
             pp.off_g = q.off + p.off_g;
             Job base = base_job(&q.r.in, &q.r.field, q.r.order, &S->cfg.opts, pp, S->arena_base);
             if (S->lut) {
@@ -284,6 +321,9 @@ void loop(Server *S)
                 Job js = base;
                 js.smap_base = tot_smap;
                 tot_smap += scale_map_blocks(q.r.in.H, q.r.in.W);
+                js.blk_base = tot_plan;   // the scale-map table also drives the block plan
+                js.req_counts = S->d_counts + 2 * q.slot;
+                tot_plan += fd_blocks_job(js);
                 b.h[nsmap++] = js;
             }
             Job jp = base;
@@ -302,9 +342,33 @@ void loop(Server *S)
             if (q.pass == q.r.order) b.finishing.push_back(id);
             b.running.push_back(id);
         }
-        if (!launch_step(S, b, nsmap, tot_smap, counts, tot_tiles, tot_blk)) {
+        if (!launch_step(S, b, nsmap, tot_smap, tot_plan, counts, tot_tiles, tot_blk)) {
+            // nothing more runs for the requests in flight: wait for whatever did reach
+            // the device, then end them all with SVF_EHIP and give their memory back
+            hipStreamSynchronize(S->stream);
+            const double t = now_us();
             std::lock_guard<std::mutex> lk(S->mu);
             S->err = "step launch failed";
+            for (uint64_t id : S->inflight) {
+                Req &q = S->reqs[id];
+                q.done = true;
+                q.status = SVF_EHIP;
+                q.t_done = t;
+                release(S, q);
+                S->stats.completed++;
+                note_finished(S, id);
+            }
+            S->inflight.clear();
+            for (auto &sb : S->buf) {
+                sb.finishing.clear();
+                sb.running.clear();
+                sb.pending = false;
+            }
+            note_idle(S, t);
+            S->stats.steps++;
+            S->cv_done.notify_all();
+            ++k;
+            continue;
         }
         b.pending = true;
         {
@@ -347,17 +411,23 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
         e = hipMalloc(reinterpret_cast<void **>(&S->lut), (size_t)c.opts.lut_nodes * c.opts.lut_nodes * 16);
         if (e == hipSuccess) e = launch_lut_build(S->lut, c.opts.lut_nodes, c.opts.lut_eps_rel, S->stream);
     }
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_counts), sizeof(uint32_t) * 2 * S->cap);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipMalloc(&S->buf[i].d, sizeof(Job) * kTables * S->cap);
         if (e == hipSuccess) e = hipHostMalloc(&S->buf[i].h, sizeof(Job) * kTables * S->cap, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&S->buf[i].h_counts), sizeof(uint32_t) * 2 * S->cap,
+                              hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&S->buf[i].ev, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         for (auto &b : S->buf) {
             if (b.d) hipFree(b.d);
             if (b.h) hipHostFree(b.h);
+            if (b.h_counts) hipHostFree(b.h_counts);
             if (b.ev) hipEventDestroy(b.ev);
         }
+        if (S->d_counts) hipFree(S->d_counts);
         if (S->arena_base) hipFree(S->arena_base);
         if (S->lut) hipFree(S->lut);
         if (S->stream) hipStreamDestroy(S->stream);
@@ -365,6 +435,8 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
         return fail(ctx, SVF_ENOMEM, "server allocation: %s", hipGetErrorString(e));
     }
     S->arena.reset(c.hbm_budget_bytes);
+    for (int i = S->cap - 1; i >= 0; --i) S->free_slots.push_back(i);
+    S->keep_finished = 4 * (size_t)c.queue_capacity + 1024;
     ctx->server = S;
     S->th = std::thread(loop, S);
     return SVF_OK;
@@ -437,13 +509,18 @@ svf_status svf_server_wait(svf_ctx *ctx, uint64_t id, svf_result *res, double ti
     std::unique_lock<std::mutex> lk(S->mu);
     auto it = S->reqs.find(id);
     if (it == S->reqs.end()) return fail(ctx, SVF_EINVAL, "unknown request id");
-    auto pred = [&] { return S->reqs[id].done; };
+    auto pred = [&] {
+        auto f = S->reqs.find(id);
+        return f == S->reqs.end() || f->second.done;
+    };
     if (timeout_s < 0) S->cv_done.wait(lk, pred);
     else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) {
         fill_result(S->reqs[id], res);
         return SVF_EBUSY;
     }
-    fill_result(S->reqs[id], res);
+    it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(ctx, SVF_EINVAL, "request %llu is no longer kept", (unsigned long long)id);
+    fill_result(it->second, res);
     return SVF_OK;
 }
 
@@ -466,6 +543,7 @@ svf_status svf_server_cancel(svf_ctx *ctx, uint64_t id)
         q.status = SVF_ECANCELLED;
         q.t_done = t;
         S->stats.cancelled++;
+        note_finished(S, id);
     } else {                      // in flight: no further pass is launched
         q.cancelled = true;
         if (q.pending == 0) end_cancelled(S, id, q, t);
@@ -501,8 +579,10 @@ svf_status svf_server_stop(svf_ctx *ctx)
     for (auto &b : S->buf) {
         hipFree(b.d);
         hipHostFree(b.h);
+        hipHostFree(b.h_counts);
         hipEventDestroy(b.ev);
     }
+    hipFree(S->d_counts);
     hipFree(S->arena_base);
     if (S->lut) hipFree(S->lut);
     hipStreamDestroy(S->stream);

@@ -1,0 +1,137 @@
+"""GPU: outputs that cannot be computed are marked, never silently wrong.
+
+- Pixels whose pass support exceeds opts.max_reach_px (the window a tile is
+  sized for), and SVF_FIELD_SCALES4 pixels whose scales are not finite and
+  positive, are written as NaN by svf_filter, svf_filter_batch and the server;
+  the report (svf_filter), svf_filter_batch_report and the request status say so
+  (SVF_EINVAL before SVF_ERANGE).  Every other pixel equals the oracle.
+- An output that is the input buffer itself, with the image split into bands on
+  internal streams: the first pass of a band must not overwrite input rows that
+  a neighbouring band's pre-integration still reads (bitwise equal to the
+  out-of-place one-band result).
+"""
+import numpy as np
+import pytest
+
+from paper_1003_2022_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1003_2022_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+CAP = 32   # max_reach_px of these tests
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def scales_case(invalid: bool):
+    """96 x 112 image; scales 3 px except a 5 x 5 patch of 60 px (support half-width
+    0.5 (60 + 120 / sqrt2) = 72 px > CAP) and, optionally, one pixel with a1 < 0."""
+    H, W = 96, 112
+    img = I.uniform_image(H, W, 5100)
+    a = np.full((H, W, 4), 3.0, np.float32)
+    a[40:45, 50:55] = 60.0
+    bad = np.zeros((H, W), bool)
+    bad[40:45, 50:55] = True
+    if invalid:
+        a[10, 20, 0] = -1.0
+        bad[10, 20] = True
+    good = a.copy()
+    good[bad] = 3.0   # the oracle sees harmless scales there; other outputs do not depend on them
+    ref = oracle.filter(img, good, oracle.FIELD_SCALES4, 1)
+    return img, a, bad, ref
+
+
+def check_marked(out, bad, ref):
+    assert np.isnan(out[bad]).all(), "a pixel beyond the reach or with invalid scales is not NaN"
+    assert np.isfinite(out[~bad]).all()
+    rel = np.abs(out[~bad] - ref[~bad]) / np.maximum(np.abs(ref[~bad]), 1e-3 * np.abs(ref).max())
+    assert rel.max() <= 1e-5, rel.max()
+
+
+@pytest.mark.parametrize("invalid", [False, True])
+def test_single_marks_overflow_and_invalid(ctx, invalid):
+    img, a, bad, ref = scales_case(invalid)
+    out, st, rep = P.filter_tensor(ctx, to_dev(img), to_dev(a), P.SVF_FIELD_SCALES4, 1, report=True,
+                                   max_reach_px=CAP, tile=64)
+    torch.cuda.synchronize()
+    assert rep.overflow_px == 25 and rep.invalid_px == (1 if invalid else 0)
+    assert st == (P.SVF_EINVAL if invalid else P.SVF_ERANGE)
+    check_marked(out.cpu().numpy(), bad, ref)
+    # no report asked for: the same NaN marks
+    out2 = P.filter_tensor(ctx, to_dev(img), to_dev(a), P.SVF_FIELD_SCALES4, 1, max_reach_px=CAP, tile=64)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np.isnan(out2.cpu().numpy()), bad)
+
+
+def test_batch_and_server_mark_overflow(ctx):
+    img, a, bad, ref = scales_case(False)
+    img_ok = I.uniform_image(64, 80, 5101)
+    a_ok = np.full((64, 80, 4), 2.5, np.float32)
+    ti, ta, ti2, ta2 = to_dev(img), to_dev(a), to_dev(img_ok), to_dev(a_ok)
+    outs = [torch.empty_like(ti2), torch.empty_like(ti)]
+    o = P.default_opts(max_reach_px=CAP)
+    P.svf_filter_batch(ctx, [P.image_of(ti2), P.image_of(ti)],
+                       [P.field_of(ta2, P.SVF_FIELD_SCALES4), P.field_of(ta, P.SVF_FIELD_SCALES4)], [1, 1], o,
+                       [P.image_of(t) for t in outs], torch.cuda.current_stream())
+    st, reps = P.svf_filter_batch_report(ctx, 2)
+    assert st == P.SVF_ERANGE
+    assert reps[0].overflow_px == 0 and reps[1].overflow_px == 25 and reps[1].invalid_px == 0
+    got = outs[1].cpu().numpy()
+    check_marked(got, bad, ref)
+    assert np.isfinite(outs[0].cpu().numpy()).all()
+    # the server: the request ends with SVF_ERANGE and the same output
+    cfg = P.svf_server_cfg()
+    cfg.max_inflight = 4
+    cfg.queue_capacity = 16
+    cfg.hbm_budget_bytes = 1 << 30
+    cfg.opts = o
+    P.svf_server_start(ctx, cfg)
+    try:
+        so = torch.empty_like(ti)
+        rid = P.svf_server_submit(ctx, P.server_request(ti, ta, P.SVF_FIELD_SCALES4, 1, so))
+        so2 = torch.empty_like(ti2)
+        rid2 = P.svf_server_submit(ctx, P.server_request(ti2, ta2, P.SVF_FIELD_SCALES4, 1, so2))
+        res = P.svf_server_wait(ctx, rid, 60.0)
+        res2 = P.svf_server_wait(ctx, rid2, 60.0)
+    finally:
+        P.svf_server_stop(ctx)
+    assert res.done and res.status == P.SVF_ERANGE
+    assert res2.done and res2.status == P.SVF_OK
+    sgot = so.cpu().numpy()
+    assert np.array_equal(np.isnan(sgot), bad)
+    assert np.array_equal(sgot[~bad], got[~bad])
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_bands_in_place(ctx, order):
+    # 2048 x 1536, 64-px tiles: 32 tile rows in 8 bands; out is the input buffer
+    H, W = 2048, 1536
+    img = I.uniform_image(H, W, 5110)
+    fld = I.srt_field(H, W, 5110, (1.0, 24.0), (1.0, 6.0), corr_len=96.0)
+    tf = to_dev(fld)
+    ref = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    src = to_dev(img)
+    P.svf_filter(ctx, P.image_of(src), P.field_of(tf, P.SVF_FIELD_SRT3), 4, order,
+                 P.default_opts(tile=64, bands=1), P.image_of(ref))
+    for bands in (1, 8):
+        buf = to_dev(img)
+        P.svf_filter(ctx, P.image_of(buf), P.field_of(tf, P.SVF_FIELD_SRT3), 4, order,
+                     P.default_opts(tile=64, bands=bands), P.image_of(buf))
+        torch.cuda.synchronize()
+        assert torch.equal(buf, ref), f"in place, {bands} bands, order {order}: differs from out of place"
