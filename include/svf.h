@@ -203,6 +203,24 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
                       const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep);
 
 /*
+ * svf_filter for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, checks and results as svf_filter (bit for bit: the same kernels),
+ * without a report; it calls no allocating routine.  Its workspace is a fixed
+ * array of the library in each device's memory, 64 MiB (enough for a one-channel
+ * 512 x 512 image or a 3-channel 320 x 320 one at the default max_reach_px;
+ * svf_workspace_bytes gives the need), held until the process ends; its address
+ * on a device is looked up by svf_create.  Returns SVF_ENOMEM (nothing enqueued)
+ * when the image needs more, SVF_EUNSUPPORTED for opts.scale_map = SVF_SCALE_LUT
+ * or opts.bands > 1.  Every call on a device shares that device's array and
+ * leaves its contents behind: calls that overlap on one device (on different
+ * streams, or from different threads or contexts) race; enqueue them on one
+ * stream.  Kernel timing (svf_set_timing) does not cover these calls.
+ */
+svf_status svf_filter_noalloc(svf_ctx *ctx, const svf_image *in, const svf_field *field, int N, int order,
+                              const svf_opts *opts, svf_image *out, hipStream_t stream);
+
+/*
  * Many images in one launch sequence: n images, each with its own field and
  * order (1..3).  All tiles of all images share one scale-map launch and, per
  * pass, one pre-integration and one finite-difference launch over a device

@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
     L.svf_filter.argtypes = [vp, P(svf_image), P(svf_field), C.c_int, C.c_int, P(svf_opts), P(svf_image), vp, P(svf_report)]
     L.svf_filter_batch.restype = st
     L.svf_filter_batch.argtypes = [vp, C.c_int, P(svf_image), P(svf_field), P(C.c_int), P(svf_opts), P(svf_image), vp, C.c_int]
+    L.svf_filter_noalloc.restype = st
+    L.svf_filter_noalloc.argtypes = [vp, P(svf_image), P(svf_field), C.c_int, C.c_int, P(svf_opts), P(svf_image), vp]
     L.svf_filter_batch_report.restype = st
     L.svf_filter_batch_report.argtypes = [vp, C.c_int, P(svf_report)]
     L.svf_st_default_params.restype = None
@@ -267,6 +269,12 @@ def svf_filter_batch(ctx: Context, imgs, fields, orders, opts: svf_opts | None, 
     return ctx.check(lib().svf_filter_batch(ctx.ptr, n, IA(*imgs), FA(*fields), RA(*orders),
                                             C.byref(opts) if opts else None, OA(*outs), _stream_handle(stream),
                                             1 if use_graph else 0))
+
+
+def svf_filter_noalloc(ctx: Context, img: svf_image, field: svf_field, N: int, order: int, opts: svf_opts | None,
+                       out: svf_image, stream=None):
+    return ctx.check(lib().svf_filter_noalloc(ctx.ptr, C.byref(img), C.byref(field), N, order,
+                                              C.byref(opts) if opts else None, C.byref(out), _stream_handle(stream)))
 
 
 def svf_filter_batch_report(ctx: Context, n: int):

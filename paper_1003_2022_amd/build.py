@@ -10,7 +10,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libsvf.so"
-SOURCES = ["svf_kernels.hip", "svf_fd.hip", "svf_st.hip", "svf_runtime.cpp", "svf_batch.cpp", "svf_server.cpp", "svf_st.cpp"]
+SOURCES = ["svf_kernels.hip", "svf_fd.hip", "svf_st.hip", "svf_runtime.cpp", "svf_batch.cpp", "svf_server.cpp", "svf_st.cpp",
+           "svf_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

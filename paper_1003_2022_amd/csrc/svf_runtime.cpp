@@ -125,6 +125,26 @@ svf_status check_field(svf_ctx *ctx, const svf_field *f, int64_t H, int64_t W)
     return SVF_OK;
 }
 
+svf_status check_filter_args(svf_ctx *ctx, const svf_image *in, const svf_field *field, int N, int order,
+                             const svf_opts &o, const svf_image *out)
+{
+    if (N != 4) return fail(ctx, SVF_EUNSUPPORTED, "only N = 4 directions (ZP lattice) is supported");
+    if (order < 1 || order > 3) return fail(ctx, SVF_EINVAL, "order must be 1..3");
+    svf_status st = check_image(ctx, in, "in", false);
+    if (st) return st;
+    st = check_image(ctx, out, "out", true);
+    if (st) return st;
+    if (out->H != in->H || out->W != in->W || out->channels != in->channels)
+        return fail(ctx, SVF_EINVAL, "out must have the input's H, W and channels");
+    st = check_field(ctx, field, in->H, in->W);
+    if (st) return st;
+    st = check_opts(ctx, &o, pick_tile(in->H, in->W, o.tile));
+    if (st) return st;
+    if (o.preint == SVF_PRE_I64 && in->dtype != SVF_U16)
+        return fail(ctx, SVF_EUNSUPPORTED, "integer pre-integration needs a uint16 image");
+    return SVF_OK;
+}
+
 Plan plan_for(const svf_image *in, int order, const svf_opts *o)
 {
     Plan p;
@@ -341,6 +361,7 @@ svf_status svf_create(svf_ctx **out, int device, size_t hbm_budget_bytes)
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SVF_EHIP;
     if (hipSetDevice(device) != hipSuccess) return SVF_EHIP;
+    noalloc_setup(device);   // the fixed workspace of svf_filter_noalloc on this device (its status is kept)
     svf_ctx *c = new (std::nothrow) svf_ctx();
     if (!c) return SVF_ENOMEM;
     c->device = device;
@@ -466,23 +487,10 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
 {
     if (!ctx) return SVF_EINVAL;
     ctx->err.clear();
-    if (N != 4) return fail(ctx, SVF_EUNSUPPORTED, "only N = 4 directions (ZP lattice) is supported");
-    if (order < 1 || order > 3) return fail(ctx, SVF_EINVAL, "order must be 1..3");
     svf_opts o;
     if (opts) o = *opts; else svf_default_opts(&o);
-    svf_status st = check_image(ctx, in, "in", false);
+    svf_status st = check_filter_args(ctx, in, field, N, order, o, out);
     if (st) return st;
-    st = check_image(ctx, out, "out", true);
-    if (st) return st;
-    if (out->H != in->H || out->W != in->W || out->channels != in->channels)
-        return fail(ctx, SVF_EINVAL, "out must have the input's H, W and channels");
-    st = check_field(ctx, field, in->H, in->W);
-    if (st) return st;
-    const int T = pick_tile(in->H, in->W, o.tile);
-    st = check_opts(ctx, &o, T);
-    if (st) return st;
-    if (o.preint == SVF_PRE_I64 && in->dtype != SVF_U16)
-        return fail(ctx, SVF_EUNSUPPORTED, "integer pre-integration needs a uint16 image");
     if (rep) std::memset(rep, 0, sizeof *rep);
     if (in->H == 0 || in->W == 0) return SVF_OK;
     return svf::run_filter(ctx, in, field, order, o, out, stream, rep, 0);
@@ -492,18 +500,29 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
 
 // The filter proper on checked arguments, its workspace at ctx->ws + ws_off
 // (callers that keep their own buffers at the front of the workspace grow it to
-// ws_off + plan bytes first).
+// ws_off + plan bytes first).  With fixed_ws the workspace is that memory instead
+// and nothing is allocated: the caller has checked its size, that rep is NULL, the
+// scale map is the solve and there is one band; launches are not timed.
 svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
-                           svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off, const double *uniform_a)
+                           svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off, const double *uniform_a,
+                           unsigned char *fixed_ws)
 {
     Plan p = plan_for(in, order, &o);
-    svf_status st = ensure_workspace(ctx, ws_off + p.bytes);
-    if (st) return st;
+    svf_status st = SVF_OK;
+    if (!fixed_ws) {
+        st = ensure_workspace(ctx, ws_off + p.bytes);
+        if (st) return st;
+    }
     hipSetDevice(ctx->device);
-    unsigned char *ws = static_cast<unsigned char *>(ctx->ws) + ws_off;
+    unsigned char *ws = fixed_ws ? fixed_ws : static_cast<unsigned char *>(ctx->ws) + ws_off;
     Job j = base_job(in, field, order, &o, p, ws);
-    st = attach_lut(ctx, o, j, stream);
-    if (st) return st;
+    if (!fixed_ws) {
+        st = attach_lut(ctx, o, j, stream);
+        if (st) return st;
+    }
+    auto launch = [&](int cls, hipStream_t s, const auto &fn) -> hipError_t {
+        return fixed_ws ? fn() : timed_launch(ctx, cls, s, fn);
+    };
     j.out = static_cast<float *>(out->data);
     j.out_rs = out->row_stride;
 
@@ -531,7 +550,7 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
         return jp;
     };
 
-    const int nb = pick_bands(p, o.bands);
+    const int nb = fixed_ws ? 1 : pick_bands(p, o.bands);
     // a constant filter: the difference kernel that forms the taps once per block
     const double im = 1.0 / std::sqrt((double)order);
     double ua_pass[4] = {0, 0, 0, 0};
@@ -540,15 +559,15 @@ svf_status svf::run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *f
     const bool uniform_fd = uniform_a && !o.fd_fp32 && o.preint != SVF_PRE_I64 &&
                             fd_uniform_fits(ua_pass[0], ua_pass[1], ua_pass[2], ua_pass[3], in->channels);
     if (nb <= 1) {
-        e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(pass_job(0, 0, p.ntr), stream); });
+        e = launch(kClsScaleMap, stream, [&] { return launch_scale_map(pass_job(0, 0, p.ntr), stream); });
         if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
         e = launch_fd_plan(pass_job(0, 0, p.ntr), stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "block plan launch");
         for (int pass = 0; pass < order; ++pass) {
             const Job jp = pass_job(pass, 0, p.ntr);
-            e = timed_launch(ctx, kClsPreint, stream, [&] { return launch_preint(jp, stream); });
+            e = launch(kClsPreint, stream, [&] { return launch_preint(jp, stream); });
             if (e != hipSuccess) return hip_fail(ctx, e, "pre-integration launch");
-            e = timed_launch(ctx, kClsFd, stream, [&] { return uniform_fd ? launch_fd_uniform(jp, ua_pass, stream) : launch_fd(jp, stream); });
+            e = launch(kClsFd, stream, [&] { return uniform_fd ? launch_fd_uniform(jp, ua_pass, stream) : launch_fd(jp, stream); });
             if (e != hipSuccess) return hip_fail(ctx, e, "finite-difference launch");
         }
     } else {

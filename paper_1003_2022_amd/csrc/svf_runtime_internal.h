@@ -59,6 +59,9 @@ int pick_tile(int64_t H, int64_t W, int requested);
 svf_status check_opts(svf_ctx *ctx, const svf_opts *o, int T);
 svf_status check_image(svf_ctx *ctx, const svf_image *im, const char *what, bool output);
 svf_status check_field(svf_ctx *ctx, const svf_field *f, int64_t H, int64_t W);
+// svf_filter's argument checks (N, order, images, field, options)
+svf_status check_filter_args(svf_ctx *ctx, const svf_image *in, const svf_field *field, int N, int order,
+                             const svf_opts &o, const svf_image *out);
 Plan plan_for(const svf_image *in, int order, const svf_opts *o);
 svf_status ensure_workspace(svf_ctx *ctx, size_t bytes);
 svf_status ensure_pinned(svf_ctx *ctx, size_t bytes);
@@ -69,7 +72,11 @@ Job base_job(const svf_image *in, const svf_field *field, int order, const svf_o
 svf_status attach_lut(svf_ctx *ctx, const svf_opts &o, Job &j, hipStream_t stream);
 svf_status run_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field, int order, const svf_opts &o,
                       svf_image *out, hipStream_t stream, svf_report *rep, size_t ws_off,
-                      const double *uniform_a = nullptr);   // the field's scales where they are all equal
+                      const double *uniform_a = nullptr,    // the field's scales where they are all equal
+                      unsigned char *fixed_ws = nullptr);   // workspace given by the caller: nothing allocated
+// svf_filter_noalloc (svf_noalloc.hip): find the device address of the library's
+// fixed workspace on `device` (current); called once per device by svf_create
+hipError_t noalloc_setup(int device);
 
 }  // namespace svf
 
