@@ -96,25 +96,70 @@ def fd_traffic_per_launch():
     return float(b.group(1)), str(TRAFFIC_SUMMARY.relative_to(ROOT))
 
 
-def cpu_baseline(img, fld, kind):
-    """Time the CPU oracle (binary64 fast algorithm, OpenMP) on a bounded sample of the workload."""
+CPU_RECT = (512, 512, 3072, 3072)        # the oracle's sample of the 4096^2 workload (rows, cols, h, w)
+CPU_RECT_1T = (1792, 1792, 256, 256)     # its single-thread sample
+
+
+def cpu_model():
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(img, fld, kind, f32_out, img16=None, u16_out=None):
+    """Time the CPU oracle (binary64 fast algorithm, OpenMP) on a bounded sample of the workload, with
+    every core the process may run on and with one thread, and compare the GPU outputs of every
+    pre-integration variant with it element by element on the sample.
+
+    f32_out / u16_out: {variant name: GPU output on CPU_RECT} for the FP32 image and the uint16 image."""
     import oracle
 
     oracle.build()
-    r0 = c0 = 512
-    side = 3072
+    cores = len(os.sched_getaffinity(0))
+    r0, c0, h, w = CPU_RECT
+    used = oracle.set_threads(cores)
     t = time.perf_counter()
-    out = oracle.filter_region(img, fld, kind, ORDER, (r0, c0, side, side))
+    ref = oracle.filter_region(img, fld, kind, ORDER, CPU_RECT)
     dt = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    parity = []
+
+    def check(src, outs, ref_):
+        for name, got in outs.items():
+            mx, rms = rel_errors(got, ref_)
+            bar = name != "f64+fd_fp32"   # the binary32 difference is reported only
+            parity.append({"input": src, "preint": name, "max_rel": mx, "rms_rel": rms,
+                           "within_1e-5_1e-6": (mx <= 1e-5 and rms <= 1e-6) if bar else None})
+            log(f"parity vs oracle {src}/{name}: max rel {mx:.2e} rms {rms:.2e}")
+
+    check("f32", f32_out, ref)
+    if img16 is not None and u16_out:
+        ref16 = oracle.filter_region(img16.astype(np.float64), fld, kind, ORDER, CPU_RECT)
+        check("u16", u16_out, ref16)
+    # one thread on a smaller sample
+    oracle.set_threads(1)
+    r1, c1, h1, w1 = CPU_RECT_1T
+    t = time.perf_counter()
+    oracle.filter_region(img, fld, kind, ORDER, CPU_RECT_1T)
+    dt1 = time.perf_counter() - t
+    oracle.set_threads(cores)
     return {
-        "value": round(side * side / dt / 1e6, 4),
+        "value": round(h * w / dt / 1e6, 4),
         "unit": "Mpixel/s",
-        "cores": cores,
+        "cores": used,
         "kind": "oracle",
-        "sample": f"{side}x{side} output pixels at ({r0},{c0}) of the same 4096x4096 order-2 workload "
-                  f"(the oracle also computes the pass-1 region the sample depends on), {dt:.1f} s",
-        "checksum": float(np.mean(out)),
+        "sample": f"{h}x{w} output pixels at ({r0},{c0}) of the same 4096x4096 order-2 workload "
+                  f"(the oracle also computes the pass-1 region the sample depends on), {dt:.1f} s on {used} threads",
+        "cpu_model": cpu_model(),
+        "affinity_cores": cores,
+        "single_thread": {"value": round(h1 * w1 / dt1 / 1e6, 4), "unit": "Mpixel/s", "cores": 1,
+                          "sample": f"{h1}x{w1} output pixels at ({r1},{c1}), {dt1:.1f} s"},
+        "parity_vs_oracle": {"region": list(CPU_RECT), "tolerance": "max rel 1e-5, RMS rel 1e-6 per pixel "
+                             "(relative to max(|ref|, 1e-3 max|ref|)); the FP32 difference is reported only",
+                             "variants": parity},
     }
 
 
@@ -410,8 +455,9 @@ def rel_errors(got, ref):
 
 def precision_leg(P, I, ctx, img, fld, ti, tf, torch, steps=5):
     """Every pre-integration variant on the 4096^2 workload, FP32 and uint16 inputs: time, and the difference
-    from the FP64 (FP32 input) or int64 (uint16 input) variant over the whole image.  Each variant's parity
-    with the CPU oracle is checked by the full-size tests, not here."""
+    from the FP64 (FP32 input) or int64 (uint16 input) variant over the whole image.  Returns the leg's
+    record, the uint16 image and each variant's output on CPU_RECT (compared with the oracle in
+    cpu_baseline)."""
     img16 = I.uniform_image(H, W, SEED + 1, dtype="u16")
     t16 = torch.from_numpy(img16).to(ti.device)
     variants = [("f32", "f64", P.SVF_PRE_F64, 0), ("f32", "f32c", P.SVF_PRE_F32C, 0), ("f32", "f64+fd_fp32", P.SVF_PRE_F64, 1),
@@ -424,6 +470,8 @@ def precision_leg(P, I, ctx, img, fld, ti, tf, torch, steps=5):
                        "variants (per pixel, floor 1e-3 of the largest value)",
            "variants": []}
     refs = {}
+    crops = {"f32": {}, "u16": {}}
+    r0, c0, h, w = CPU_RECT
     for src, name, pre, fd32 in variants:
         o = P.default_opts(preint=pre, fd_fp32=fd32)
         im_d = P.image_of(ti if src == "f32" else t16)
@@ -435,13 +483,14 @@ def precision_leg(P, I, ctx, img, fld, ti, tf, torch, steps=5):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / steps
         o_np = out.cpu().numpy()
+        crops[src][name] = o_np[r0:r0 + h, c0:c0 + w].copy()
         if src not in refs:
             refs[src] = o_np.copy()
         mx, rms = rel_errors(o_np, refs[src])
         res["variants"].append({"input": src, "preint": name, "max_rel_diff": mx, "rms_rel_diff": rms,
                                 "ms_per_step": round(ms, 3), "Mpixel_s": round(H * W / (ms * 1e-3) / 1e6, 1)})
         log(f"precision {src}/{name}: max rel diff {mx:.2e} rms {rms:.2e}  {ms:.3f} ms/step")
-    return res
+    return res, img16, crops
 
 
 def cov_of_scales(a):
@@ -643,13 +692,26 @@ def main():
         },
         "roofline": roofline,
         "hbm_roofline_frac_72Bpx": round(ALGO_BYTES_PER_PX_PASS * ORDER * H * W / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        # the metric's "% HBM roofline": the whole step against HBM, algorithmic bytes 36 B per pixel and pass
+        "roofline_hbm": {
+            "scope": "whole step: scale map, then per pass pre-integration and finite difference",
+            "bound": "hbm",
+            "achieved": round(ALGO_BYTES_PER_PX_PASS * ORDER * H * W / (ms * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(ALGO_BYTES_PER_PX_PASS * ORDER * H * W / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "algorithmic_bytes_per_px": ALGO_BYTES_PER_PX_PASS * ORDER,
+        },
         "kernel_avg_us": {k: round(tot / max(n, 1) * 1e3, 2) for k, (tot, n) in kt.items()},
         "ms_per_step_one_band": round(ms_seq, 4),
         "report": {"clamped_px": rep.clamped_px, "eps_active_px": rep.eps_active_px,
                    "max_reach_px": round(rep.max_reach_px, 2)},
     }
+    r0c, c0c, hc, wc = CPU_RECT
+    f32_crops, img16, u16_crops = {"f64": to.cpu().numpy()[r0c:r0c + hc, c0c:c0c + wc].copy()}, None, None
     if not args.no_precision:
-        line["precision"] = precision_leg(P, I, ctx, img, fld, ti, tf, torch)
+        line["precision"], img16, crops = precision_leg(P, I, ctx, img, fld, ti, tf, torch)
+        f32_crops, u16_crops = crops["f32"], crops["u16"]
     if not args.no_table2:
         line["table2"] = table2_leg(P, I, ctx, torch)
     if not args.no_lut:
@@ -663,7 +725,7 @@ def main():
                                       args.serve_step_mpx)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
-        line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3)
+        line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3, f32_crops, img16, u16_crops)
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -102,8 +102,15 @@ def lib():
         L.svfo_table1_tap.argtypes = [dp, C.c_int, dp, dp, dp]
         L.svfo_tau.restype = None
         L.svfo_tau.argtypes = [dp, dp, dp]
+        L.svfo_set_threads.restype = C.c_int
+        L.svfo_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (n <= 0: the runtime's default); returns the count in use."""
+    return int(lib().svfo_set_threads(int(n)))
 
 
 def _dp(x: np.ndarray):

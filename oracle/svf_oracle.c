@@ -36,6 +36,7 @@
  * u4 = (-1,1)/sqrt2 (Sec. 3, eq. before (final_eqn)).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -595,4 +596,12 @@ int svfo_scale_field(const float *field, int kind, long H, long W, int order, do
     if (n_eps) *n_eps = nep;
     if (n_invalid) *n_invalid = ninv;
     return ninv ? -1 : 0;
+}
+
+/* Threads of the OpenMP loops above (n <= 0 leaves the runtime's choice); returns the
+ * count the next parallel loops use.  Changes no arithmetic. */
+int svfo_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
