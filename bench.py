@@ -16,10 +16,11 @@ Beside it, in the same JSON line:
                 each with its own field: one graph-replayed batched launch
                 against 64 svf_filter calls;
   serving       Poisson arrivals of 3-channel images 512..4096 px (aspect 1:1 to
-                1:2), orders 1-3, at two request rates: the continuous-batching
-                server against a FIFO of svf_filter calls (one image per
-                launch), p50/p99 latency from arrival, and the saturated
-                throughput of both;
+                1:2), orders 1-3: the saturated throughput of the
+                continuous-batching server (steps replayed from captured HIP
+                graphs) and of a FIFO of svf_filter calls (one image per
+                launch), then 2000 requests at 25/50/80/95 % of the server's
+                saturated rate, p50/p99 latency from arrival for both;
   precision     each pre-integration variant (FP64, compensated FP32, int64 for
                 uint16 input) and the FP32 finite difference on the same
                 workload: ms per step and the max / RMS relative difference
@@ -41,7 +42,7 @@ Beside it, in the same JSON line:
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve] [--no-precision]
                     [--no-smooth] [--no-lut] [--no-table2]
-                    [--calib-copy] [--preint f64|f32c] [--tile T] [--qps Q] [--serve-seconds S]
+                    [--calib-copy] [--preint f64|f32c] [--tile T] [--loads F,...] [--serve-requests N]
 """
 from __future__ import annotations
 
@@ -248,6 +249,7 @@ def serve_server(P, ctx, img3, fld, reqs, arrivals, torch, step_mpx=0):
     cfg.max_inflight = 16
     cfg.queue_capacity = len(reqs) + 16
     cfg.hbm_budget_bytes = 48 << 30
+    cfg.use_graph = 1
     cfg.step_mpixels = step_mpx
     cfg.opts = P.default_opts()
     P.svf_server_start(ctx, cfg)
@@ -305,51 +307,57 @@ def serve_fifo(P, ctx, img3, fld, reqs, arrivals, torch):
     return lats, last - float(arrivals[0])
 
 
-def serving_leg(P, I, ctx, fld_dev, torch, qps, seconds, step_mpx=0, n_sat=120):
+def serving_leg(P, I, ctx, fld_dev, torch, loads, n_req, step_mpx=0, n_sat=200):
+    """Saturated throughput of the server, then Poisson arrivals at fractions `loads` of it (n_req requests per
+    load point), server against one image per launch at each."""
     dev = fld_dev.device
     t0 = time.perf_counter()
     img3 = torch.from_numpy(I.uniform_image(H, W, SEED + 5, channels=3)).to(dev)
     log(f"serving: 3-channel pool generated in {time.perf_counter() - t0:.1f} s")
     rng = np.random.default_rng(SEED + 5)
-    n = max(1, int(max(qps) * seconds))
-    reqs = serving_requests(rng, n)
-    arrivals0 = np.cumsum(rng.exponential(1.0, n))   # unit-rate Poisson process, scaled per load
+    reqs = serving_requests(rng, max(n_req, n_sat))
+    arrivals0 = np.cumsum(rng.exponential(1.0, len(reqs)))   # unit-rate Poisson process, scaled per load
     arrivals0 -= arrivals0[0]
-    px = sum(h * w for h, w, *_ in reqs)
     # warm both paths on the largest shape (workspace growth is not part of a request)
     big = (4096, 4096, 0, 0, 3)
     serve_fifo(P, ctx, img3, fld_dev, [big], np.zeros(1), torch)
     serve_server(P, ctx, img3, fld_dev, [big], np.zeros(1), torch, step_mpx)
-    out = {
-        "workload": f"Poisson arrivals at {'/'.join(f'{q:g}' for q in qps)} req/s ({n} requests): 3-channel FP32 images, "
-                    "long side uniform 512-4096 px, aspect 1:1-1:2, order uniform 1-3, own crops of a smooth "
-                    "field (sigma 1-32 px, rho 1-6), f64 pre-integration",
-        "requests": n, "pixels": int(px), "channels": 3,
-        "server_config": {"max_inflight": 16, "step_mpixels": step_mpx or "default (64)"},
-    }
-    out["loads"] = []
-    for q in qps:
-        arr = arrivals0 / q
-        lat_s, span_s, st = serve_server(P, ctx, img3, fld_dev, reqs, arr, torch, step_mpx)
-        lat_f, span_f = serve_fifo(P, ctx, img3, fld_dev, reqs, arr, torch)
-        rec = {"qps": q, "offered_Mpixel_s": round(px / float(arr[-1]) / 1e6, 1),
-               "server": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "Mpixel_s": round(px / span_s / 1e6, 1),
-                          "steps": int(st.steps)},
-               "one_image_per_launch": {"p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
-                                        "Mpixel_s": round(px / span_f / 1e6, 1)}}
-        out["loads"].append(rec)
-        log(f"serving @ {q:g} req/s: server p50 {rec['server']['p50_ms']} ms p99 {rec['server']['p99_ms']} ms; "
-            f"per-launch p50 {rec['one_image_per_launch']['p50_ms']} ms p99 {rec['one_image_per_launch']['p99_ms']} ms")
-    # saturated: every request present at t = 0
+    # saturated: n_sat requests present at t = 0
     sat = reqs[:n_sat]
     z = np.zeros(len(sat))
     spx = sum(h * w for h, w, *_ in sat)
     _, span_s, _ = serve_server(P, ctx, img3, fld_dev, sat, z, torch, step_mpx)
     _, span_f = serve_fifo(P, ctx, img3, fld_dev, sat, z, torch)
-    out["saturated"] = {"requests": len(sat), "server_Mpixel_s": round(spx / span_s / 1e6, 1),
-                        "one_image_per_launch_Mpixel_s": round(spx / span_f / 1e6, 1)}
-    log(f"saturated: server {out['saturated']['server_Mpixel_s']} Mpx/s, "
+    cap_px = spx / span_s
+    work = reqs[:n_req]
+    px = sum(h * w for h, w, *_ in work)
+    cap_rps = cap_px / (px / len(work))
+    out = {
+        "workload": f"Poisson arrivals, {n_req} requests per load point: 3-channel FP32 images, long side uniform "
+                    "512-4096 px, aspect 1:1-1:2, order uniform 1-3, own crops of a smooth field (sigma 1-32 px, "
+                    "rho 1-6), f64 pre-integration; loads are fractions of the server's saturated throughput",
+        "requests": n_req, "pixels": int(px), "channels": 3,
+        "server_config": {"max_inflight": 16, "step_mpixels": step_mpx or "default (64)", "use_graph": 1},
+        "saturated": {"requests": len(sat), "server_Mpixel_s": round(spx / span_s / 1e6, 1),
+                      "one_image_per_launch_Mpixel_s": round(spx / span_f / 1e6, 1),
+                      "server_capacity_req_s": round(cap_rps, 1)},
+        "loads": [],
+    }
+    log(f"saturated: server {out['saturated']['server_Mpixel_s']} Mpx/s ({cap_rps:.0f} req/s), "
         f"per-launch {out['saturated']['one_image_per_launch_Mpixel_s']} Mpx/s")
+    for f in loads:
+        q = f * cap_rps
+        arr = arrivals0[:n_req] / q
+        lat_s, span_s, st = serve_server(P, ctx, img3, fld_dev, work, arr, torch, step_mpx)
+        lat_f, span_f = serve_fifo(P, ctx, img3, fld_dev, work, arr, torch)
+        rec = {"load": f, "qps": round(q, 1), "offered_Mpixel_s": round(px / float(arr[-1]) / 1e6, 1),
+               "server": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99), "Mpixel_s": round(px / span_s / 1e6, 1),
+                          "steps": int(st.steps)},
+               "one_image_per_launch": {"p50_ms": pct(lat_f, 50), "p99_ms": pct(lat_f, 99),
+                                        "Mpixel_s": round(px / span_f / 1e6, 1)}}
+        out["loads"].append(rec)
+        log(f"serving @ {f:.0%} ({q:.0f} req/s): server p50 {rec['server']['p50_ms']} ms p99 {rec['server']['p99_ms']} ms; "
+            f"per-launch p50 {rec['one_image_per_launch']['p50_ms']} ms p99 {rec['one_image_per_launch']['p99_ms']} ms")
     return out
 
 
@@ -573,8 +581,9 @@ def main():
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
     ap.add_argument("--tile", type=int, default=0, help="output tile side (0 = library default)")
     ap.add_argument("--bands", type=int, default=0, help="concurrent bands of tile rows (0 = library default: one)")
-    ap.add_argument("--qps", default="400,600", help="serving arrival rates (requests/s), comma-separated")
-    ap.add_argument("--serve-seconds", type=float, default=5.0, help="duration of the highest-rate arrival stream")
+    ap.add_argument("--loads", default="0.25,0.5,0.8,0.95",
+                    help="serving arrival rates as fractions of the server's saturated throughput, comma-separated")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per serving load point")
     ap.add_argument("--serve-step-mpx", type=int, default=0, help="server work per step (Mpixel x channels, 0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -721,8 +730,8 @@ def main():
     if not args.no_batch:
         line["batch"] = batch_leg(P, I, ctx, ti, torch)
     if not args.no_serve:
-        line["serving"] = serving_leg(P, I, ctx, tf, torch, [float(q) for q in args.qps.split(",")], args.serve_seconds,
-                                      args.serve_step_mpx)
+        line["serving"] = serving_leg(P, I, ctx, tf, torch, [float(q) for q in args.loads.split(",")],
+                                      args.serve_requests, args.serve_step_mpx)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3, f32_crops, img16, u16_crops)

@@ -316,7 +316,10 @@ typedef struct {
     int32_t step_mpixels;       /* work per scheduler step: passes are taken in admission order until
                                    their pixels x channels reach this many million (the oldest always
                                    runs; later, smaller passes fill what is left); <= 0: 64 */
-    int32_t reserved1;
+    int32_t use_graph;          /* != 0: each step's launch sequence (descriptor upload, scale map, block
+                                   plan, pre-integration, difference, counter download) is captured once
+                                   per kernel set and grid sizes as a HIP graph and replayed; the kernels
+                                   read the step's sizes from device memory */
     svf_opts opts;              /* options of every request */
 } svf_server_cfg;
 

@@ -55,7 +55,7 @@ class svf_report(C.Structure):
 
 class svf_server_cfg(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("queue_capacity", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
-                ("step_mpixels", C.c_int32), ("reserved1", C.c_int32), ("opts", svf_opts)]
+                ("step_mpixels", C.c_int32), ("use_graph", C.c_int32), ("opts", svf_opts)]
 
 
 class svf_request(C.Structure):

@@ -360,12 +360,16 @@ __global__ __launch_bounds__(256) void k_fd_plan(Job J, int nblocks)
 }
 
 // one thread per block of any image of the table (blk_base: the job's first block)
-__global__ __launch_bounds__(256) void k_fd_plan_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(256) void k_fd_plan_batch(const Job *jobs, int n, int total, const BatchDims *dims)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= total) return;
-    const int j = find_job(jobs, n, b, 1);
-    fd_plan_block(jobs[j], b - jobs[j].blk_base);
+    if (dims) {
+        n = dims->n;
+        total = dims->total;
+    }
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < total; b += gridDim.x * blockDim.x) {
+        const int j = find_job(jobs, n, b, 1);
+        fd_plan_block(jobs[j], b - jobs[j].blk_base);
+    }
 }
 
 // 16 bytes per lane from a buffer straight into LDS: lane l writes dst + 16 l
@@ -556,7 +560,7 @@ __device__ __forceinline__ void fd_block(const Job &J, int gb, double (*lds)[NCH
 }
 
 template <int PRE, int NCH, typename R>
-__global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPreF64 && NCH == 1 ? 5 : 1, 8))) void k_fd(Job J, int nblocks)
 {
     __shared__ double lds[fd_buffers<PRE, NCH>()][NCH][kRegPad];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -564,15 +568,28 @@ __global__ __launch_bounds__(256) void k_fd(Job J, int nblocks)
     if (lb < nblocks) fd_block<PRE, NCH, R>(J, J.tr0 * J.ntc * bpt + lb, lds);
 }
 
-// one work-group per 16 x 16 block of any image of the table (all with NCH channels)
+// One work-group per 16 x 16 block of any image of the table (all with NCH
+// channels); the grid may be larger than the work list (the server's captured
+// graphs round it up), surplus groups exit.  XCD-aware order as in k_fd: work-group
+// w runs on XCD w mod 8, and each XCD takes one contiguous eighth of the tile-major
+// block list (eighths of the work list itself, not of the grid: a rounded-up grid
+// would otherwise leave the last XCDs without work).
 template <int PRE, int NCH, typename R>
-__global__ __launch_bounds__(256) void k_fd_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPreF64 && NCH == 1 ? 5 : 1, 8))) void k_fd_batch(
+    const Job *jobs, int n, int total, const BatchDims *dims)
 {
     __shared__ double lds[fd_buffers<PRE, NCH>()][NCH][kRegPad];
-    const int b = blockIdx.x;
-    if (b >= total) return;
+    if (dims) {
+        n = dims->n;
+        total = dims->total;
+    }
+    const int per = (total + 7) >> 3, slot = blockIdx.x >> 3;
+    const int b = (blockIdx.x & 7) * per + slot;
+    if (slot >= per || b >= total) return;
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 1));
-    const Job &J = jobs[j];
+    // a copy in registers: read from the table in memory, the descriptor would be
+    // read again after every load into LDS (which may write any memory)
+    const Job J = jobs[j];
     fd_block<PRE, NCH, R>(J, b - J.blk_base, lds);
 }
 
@@ -760,10 +777,13 @@ hipError_t launch_fd_plan(const Job &j, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fd_plan_batch(const Job *jobs, int n, int total_blocks, hipStream_t s)
+hipError_t launch_fd_plan_batch(const Job *jobs, int n, int total_blocks, hipStream_t s, const BatchDims *dims, int grid)
 {
-    if (total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fd_plan_batch, dim3((total_blocks + 255) / 256), dim3(256), 0, s, jobs, n, total_blocks);
+    if (!dims) {
+        if (total_blocks <= 0) return hipSuccess;
+        grid = (total_blocks + 255) / 256;
+    }
+    hipLaunchKernelGGL(k_fd_plan_batch, dim3(std::max(1, grid)), dim3(256), 0, s, jobs, n, total_blocks, dims);
     return hipGetLastError();
 }
 
@@ -789,34 +809,38 @@ hipError_t launch_fd(const Job &j, hipStream_t s)
 }
 
 template <int PRE, typename R>
-static hipError_t launch_fd_batch_pr(const Job *jobs, int n, int total, int nch, hipStream_t s)
+static hipError_t launch_fd_batch_pr(const Job *jobs, int n, int total, int grid, int nch, hipStream_t s,
+                                     const BatchDims *dims)
 {
     switch (nch) {
-    case 1: hipLaunchKernelGGL((k_fd_batch<PRE, 1, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
-    case 2: hipLaunchKernelGGL((k_fd_batch<PRE, 2, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
-    case 3: hipLaunchKernelGGL((k_fd_batch<PRE, 3, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
-    case 4: hipLaunchKernelGGL((k_fd_batch<PRE, 4, R>), dim3(total), dim3(256), 0, s, jobs, n, total); break;
+    case 1: hipLaunchKernelGGL((k_fd_batch<PRE, 1, R>), dim3(grid), dim3(256), 0, s, jobs, n, total, dims); break;
+    case 2: hipLaunchKernelGGL((k_fd_batch<PRE, 2, R>), dim3(grid), dim3(256), 0, s, jobs, n, total, dims); break;
+    case 3: hipLaunchKernelGGL((k_fd_batch<PRE, 3, R>), dim3(grid), dim3(256), 0, s, jobs, n, total, dims); break;
+    case 4: hipLaunchKernelGGL((k_fd_batch<PRE, 4, R>), dim3(grid), dim3(256), 0, s, jobs, n, total, dims); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,
-                           hipStream_t s)
+                           hipStream_t s, const BatchDims *dims)
 {
-    (void)grid;   // one work-group per block of the work list
-    if (total_blocks == 0) return hipSuccess;
+    if (!dims) {   // one work-group per block of the work list
+        if (total_blocks == 0) return hipSuccess;
+        grid = total_blocks;
+    }
+    grid = (std::max(1, grid) + 7) / 8 * 8;   // whole rounds over the 8 XCDs
     if (fd_fp32) {
         switch (preint) {
-        case kPreF64: return launch_fd_batch_pr<kPreF64, float>(jobs, n, total_blocks, nch, s);
-        case kPreF32C: return launch_fd_batch_pr<kPreF32C, float>(jobs, n, total_blocks, nch, s);
-        case kPreI64: return launch_fd_batch_pr<kPreI64, float>(jobs, n, total_blocks, nch, s);
+        case kPreF64: return launch_fd_batch_pr<kPreF64, float>(jobs, n, total_blocks, grid, nch, s, dims);
+        case kPreF32C: return launch_fd_batch_pr<kPreF32C, float>(jobs, n, total_blocks, grid, nch, s, dims);
+        case kPreI64: return launch_fd_batch_pr<kPreI64, float>(jobs, n, total_blocks, grid, nch, s, dims);
         }
     } else {
         switch (preint) {
-        case kPreF64: return launch_fd_batch_pr<kPreF64, double>(jobs, n, total_blocks, nch, s);
-        case kPreF32C: return launch_fd_batch_pr<kPreF32C, double>(jobs, n, total_blocks, nch, s);
-        case kPreI64: return launch_fd_batch_pr<kPreI64, double>(jobs, n, total_blocks, nch, s);
+        case kPreF64: return launch_fd_batch_pr<kPreF64, double>(jobs, n, total_blocks, grid, nch, s, dims);
+        case kPreF32C: return launch_fd_batch_pr<kPreF32C, double>(jobs, n, total_blocks, grid, nch, s, dims);
+        case kPreI64: return launch_fd_batch_pr<kPreI64, double>(jobs, n, total_blocks, grid, nch, s, dims);
         }
     }
     return hipErrorInvalidValue;

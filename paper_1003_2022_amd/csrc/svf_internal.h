@@ -90,6 +90,13 @@ struct Job {
     double lut_eps;          // the table's floor on a^2 at s = 1
 };
 
+// Size of a batched launch read by its kernels from device memory (the server's
+// steps: one captured HIP graph then serves every step with the same kernels):
+// jobs in the table and work items over all of them.
+struct BatchDims {
+    int32_t n, total;
+};
+
 // Rectangle of lattice samples pre-integrated for one tile.
 struct Window {
     int64_t r0, c0;
@@ -143,7 +150,8 @@ hipError_t launch_preint(const Job &j, hipStream_t s);
 hipError_t launch_fd(const Job &j, hipStream_t s);
 // the finite difference's block plan (after the scale map, before the first pass)
 hipError_t launch_fd_plan(const Job &j, hipStream_t s);
-hipError_t launch_fd_plan_batch(const Job *jobs, int n, int total_blocks, hipStream_t s);
+hipError_t launch_fd_plan_batch(const Job *jobs, int n, int total_blocks, hipStream_t s, const BatchDims *dims = nullptr,
+                                int grid = 0);
 // constant filter (every pixel's scales equal; 3 channels, binary64 difference):
 // whether the staged region of a block fits, and the launch
 bool fd_uniform_fits(double a1, double a2, double a3, double a4, int channels);
@@ -152,11 +160,17 @@ hipError_t launch_fd_uniform(const Job &j, const double *pass_a, hipStream_t s);
 hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c0, int h, int w, void *g,
                                 hipStream_t s);
 // batched: `jobs` is a device table of n jobs; totals are the sums of the per-job counts
-// (persistent: `grid` work-groups loop over the work list)
-hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s);
-hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s);
+// (persistent: `grid` work-groups loop over the work list).  With dims != nullptr the
+// kernels read n and the total from it instead (device memory) and the grid is
+// `grid` as given (a graph replayed for steps of different sizes).
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s,
+                                  const BatchDims *dims = nullptr);
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s,
+                               const BatchDims *dims = nullptr);
 hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,
-                           hipStream_t s);
+                           hipStream_t s, const BatchDims *dims = nullptr);
+// zero the tile records (and request counters) of the jobs of a table (dims: as above)
+hipError_t launch_fill_jobs(const Job *jobs, int n, int grid, hipStream_t s, const BatchDims *dims = nullptr);
 
 int64_t slot_elems_for(int T, int cap);
 int scale_map_blocks(int64_t H, int64_t W);

@@ -417,8 +417,13 @@ __global__ __launch_bounds__(256) void k_scale_map_lut(Job J)
     scale_map_block<true>(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map_batch(const Job *jobs, int n, int total,
+                                                                                                    const BatchDims *dims)
 {
+    if (dims) {
+        n = dims->n;
+        total = dims->total;
+    }
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
         const Job &J = jobs[j];
@@ -426,12 +431,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
 }
 
-__global__ __launch_bounds__(256) void k_scale_map_batch_lut(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(256) void k_scale_map_batch_lut(const Job *jobs, int n, int total, const BatchDims *dims)
 {
+    if (dims) {
+        n = dims->n;
+        total = dims->total;
+    }
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
         const Job &J = jobs[j];
         scale_map_block<true>(J, b - J.smap_base);
+    }
+}
+
+// tile records and request counters of the jobs of a table
+__global__ void k_fill_jobs(const Job *jobs, int n, const BatchDims *dims)
+{
+    if (dims) n = dims->n;
+    for (int j = blockIdx.x; j < n; j += gridDim.x) {
+        const Job &J = jobs[j];
+        uint32_t *t = reinterpret_cast<uint32_t *>(J.tstat);
+        const int64_t words = (int64_t)J.ntr * J.ntc * (int64_t)(sizeof(TileStat) / 4);
+        for (int64_t i = threadIdx.x; i < words; i += blockDim.x) t[i] = 0u;
+        if (J.req_counts && threadIdx.x < 2) J.req_counts[threadIdx.x] = 0u;
     }
 }
 
@@ -964,9 +986,13 @@ __global__ __launch_bounds__(64 * kPreWaves) void k_preint(Job J)
 // the batched launches: windows of every image of the table, one work-group
 // each in turn (grid-stride)
 template <class A>
-__global__ __launch_bounds__(64 * kPreWaves) void k_preint_batch(const Job *jobs, int n, int total)
+__global__ __launch_bounds__(64 * kPreWaves) void k_preint_batch(const Job *jobs, int n, int total, const BatchDims *dims)
 {
     __shared__ typename A::T lds[4 * kPreBuf];
+    if (dims) {
+        n = dims->n;
+        total = dims->total;
+    }
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 0));
         const Job &J = jobs[j];
@@ -1102,25 +1128,43 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
     return hipGetLastError();
 }
 
-hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s)
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s,
+                                  const BatchDims *dims)
 {
-    if (total_blocks == 0) return hipSuccess;
-    grid = std::max(1, std::min(grid, total_blocks));
-    if (lut) hipLaunchKernelGGL(k_scale_map_batch_lut, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks);
-    else hipLaunchKernelGGL(k_scale_map_batch, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks);
+    if (!dims) {
+        if (total_blocks == 0) return hipSuccess;
+        grid = std::min(grid, total_blocks);
+    }
+    grid = std::max(1, grid);
+    if (lut) hipLaunchKernelGGL(k_scale_map_batch_lut, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
+    else hipLaunchKernelGGL(k_scale_map_batch, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
     return hipGetLastError();
 }
 
-hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s)
+hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s,
+                               const BatchDims *dims)
 {
-    if (total_tiles == 0) return hipSuccess;
-    grid = std::max(1, std::min(grid, total_tiles));
+    if (!dims) {
+        if (total_tiles == 0) return hipSuccess;
+        grid = std::min(grid, total_tiles);
+    }
+    grid = std::max(1, grid);
     switch (preint) {
-    case kPreF64: hipLaunchKernelGGL((k_preint_batch<ArF64>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles); break;
-    case kPreF32C: hipLaunchKernelGGL((k_preint_batch<ArF32C>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles); break;
-    case kPreI64: hipLaunchKernelGGL((k_preint_batch<ArI64>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles); break;
+    case kPreF64: hipLaunchKernelGGL((k_preint_batch<ArF64>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles, dims); break;
+    case kPreF32C: hipLaunchKernelGGL((k_preint_batch<ArF32C>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles, dims); break;
+    case kPreI64: hipLaunchKernelGGL((k_preint_batch<ArI64>), dim3(grid), dim3(64 * kPreWaves), 0, s, jobs, n, total_tiles, dims); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_jobs(const Job *jobs, int n, int grid, hipStream_t s, const BatchDims *dims)
+{
+    if (!dims) {
+        if (n == 0) return hipSuccess;
+        grid = std::min(grid, n);
+    }
+    hipLaunchKernelGGL(k_fill_jobs, dim3(std::max(1, grid)), dim3(256), 0, s, jobs, n, dims);
     return hipGetLastError();
 }
 

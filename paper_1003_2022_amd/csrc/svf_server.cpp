@@ -26,6 +26,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -39,7 +40,6 @@ namespace {
 constexpr int kTables = 1 + kMaxChannels;   // scale map + one table per channel count
 constexpr int kPersistentScale = 4096;
 constexpr int kPersistentPreint = 2048;
-constexpr int kPersistentFd = 16384;
 
 double now_us()
 {
@@ -107,9 +107,19 @@ struct Req {
     bool final_sched = false, cancelled = false;
 };
 
+// Sizes of a step's launches, read by the kernels from device memory: [0] scale map
+// (starting requests, their scale-map blocks), [1] block plan (the same requests, their
+// difference blocks), [2 + C] pre-integration and [2 + kMaxChannels + C] difference of
+// the requests with C channels (requests, windows / blocks).
+constexpr int kDims = 2 + 2 * (kMaxChannels + 1);
+
 struct StepBuf {
     Job *d = nullptr, *h = nullptr;
+    BatchDims *d_dims = nullptr, *h_dims = nullptr;
     uint32_t *h_counts = nullptr;      // pinned copy of the counter slots after this step
+    // captured step sequences of this table set, by kernel set and grid sizes
+    std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
+    std::vector<hipGraph_t> graph_defs;
     hipEvent_t ev = nullptr;
     bool pending = false;
     std::vector<uint64_t> finishing;   // requests whose last pass runs in this step
@@ -145,29 +155,91 @@ struct Server {
 
 Server *srv(svf_ctx *ctx) { return static_cast<Server *>(ctx->server); }
 
+// Grid of a launch over `work` items: at most `cap` work-groups, rounded up to a
+// power of two so that steps of similar sizes share a captured graph.
+int grid_of(int64_t work, int cap)
+{
+    int g = 1;
+    while (g < work && g < cap) g <<= 1;
+    return g;
+}
+
 // Launch one step from the tables in `b`; returns false on a HIP error.
 bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, int tot_plan, const int *counts,
                  const int *tot_tiles, const int *tot_blk)
 {
-    hipError_t e = hipMemcpyAsync(b.d, b.h, sizeof(Job) * kTables * S->cap, hipMemcpyHostToDevice, S->stream);
-    if (e != hipSuccess) return false;
-    // zero the tile records of the newly admitted requests
-    for (int i = 0; i < nsmap && e == hipSuccess; ++i) {
-        const Job &j = b.h[i];
-        e = launch_fill_u32(reinterpret_cast<uint32_t *>(j.tstat), 0u,
-                            (int64_t)j.ntr * j.ntc * (int64_t)(sizeof(TileStat) / 4), S->stream);
-        if (e == hipSuccess) e = launch_fill_u32(j.req_counts, 0u, 2, S->stream);
+    BatchDims *h = b.h_dims;
+    h[0] = {nsmap, tot_smap};
+    h[1] = {nsmap, tot_plan};
+    for (int ch = 0; ch <= kMaxChannels; ++ch) {
+        h[2 + ch] = {counts[ch], tot_tiles[ch]};
+        h[2 + kMaxChannels + 1 + ch] = {counts[ch], tot_blk[ch]};
     }
-    if (e == hipSuccess && nsmap) e = launch_scale_map_batch(b.d, nsmap, tot_smap, kPersistentScale, S->lut != nullptr, S->stream);
-    if (e == hipSuccess && nsmap) e = launch_fd_plan_batch(b.d, nsmap, tot_plan, S->stream);
-    for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
-        if (counts[ch]) e = launch_preint_batch(b.d + ch * S->cap, counts[ch], tot_tiles[ch], kPersistentPreint,
-                                                S->cfg.opts.preint, S->stream);
-    for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
-        if (counts[ch]) e = launch_fd_batch(b.d + ch * S->cap, counts[ch], tot_blk[ch], kPersistentFd,
-                                            S->cfg.opts.preint, S->cfg.opts.fd_fp32, ch, S->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b.h_counts, S->d_counts, sizeof(uint32_t) * 2 * S->cap, hipMemcpyDeviceToHost, S->stream);
+    const BatchDims *d = b.d_dims;
+    const int g_fill = grid_of(nsmap, 64), g_smap = grid_of(tot_smap, kPersistentScale);
+    const int g_plan = grid_of((tot_plan + 255) / 256, 256);
+    int g_pre[kMaxChannels + 1] = {}, g_fd[kMaxChannels + 1] = {};
+    std::string key = nsmap ? "s" + std::to_string(g_fill) + "," + std::to_string(g_smap) + "," + std::to_string(g_plan)
+                            : std::string("-");
+    for (int ch = 1; ch <= kMaxChannels; ++ch) {
+        if (!counts[ch]) continue;
+        g_pre[ch] = grid_of(tot_tiles[ch], kPersistentPreint);
+        g_fd[ch] = grid_of(tot_blk[ch], 1 << 30);   // one work-group per block (the kernel skips the surplus)
+        key += "|" + std::to_string(ch) + ":" + std::to_string(g_pre[ch]) + "," + std::to_string(g_fd[ch]);
+    }
+    auto enqueue = [&](hipStream_t st) {
+        hipError_t e = hipMemcpyAsync(b.d, b.h, sizeof(Job) * kTables * S->cap, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.d_dims, b.h_dims, sizeof(BatchDims) * kDims, hipMemcpyHostToDevice, st);
+        // the tile records and counters of the newly admitted requests start at zero
+        if (e == hipSuccess && nsmap) e = launch_fill_jobs(b.d, nsmap, g_fill, st, d + 0);
+        if (e == hipSuccess && nsmap)
+            e = launch_scale_map_batch(b.d, nsmap, tot_smap, g_smap, S->lut != nullptr, st, d + 0);
+        if (e == hipSuccess && nsmap) e = launch_fd_plan_batch(b.d, nsmap, tot_plan, st, d + 1, g_plan);
+        for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
+            if (counts[ch])
+                e = launch_preint_batch(b.d + ch * S->cap, counts[ch], tot_tiles[ch], g_pre[ch], S->cfg.opts.preint, st,
+                                        d + 2 + ch);
+        for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
+            if (counts[ch])
+                e = launch_fd_batch(b.d + ch * S->cap, counts[ch], tot_blk[ch], g_fd[ch], S->cfg.opts.preint,
+                                    S->cfg.opts.fd_fp32, ch, st, d + 2 + kMaxChannels + 1 + ch);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.h_counts, S->d_counts, sizeof(uint32_t) * 2 * S->cap, hipMemcpyDeviceToHost, st);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    if (!S->cfg.use_graph) {
+        e = enqueue(S->stream);
+    } else {
+        hipGraphExec_t exec = nullptr;
+        for (auto &g : b.graphs)
+            if (g.first == key) exec = g.second;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return false;
+            const hipError_t le = enqueue(S->stream);
+            e = hipStreamEndCapture(S->stream, &graph);
+            if (le != hipSuccess || e != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                return false;
+            }
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                hipGraphDestroy(graph);
+                return false;
+            }
+            if (b.graphs.size() >= 64) {   // keep the cache bounded
+                hipGraphExecDestroy(b.graphs.front().second);
+                hipGraphDestroy(b.graph_defs.front());
+                b.graphs.erase(b.graphs.begin());
+                b.graph_defs.erase(b.graph_defs.begin());
+            }
+            b.graphs.emplace_back(key, exec);
+            b.graph_defs.push_back(graph);
+        }
+        e = hipGraphLaunch(exec, S->stream);
+    }
     if (e == hipSuccess) e = hipEventRecord(b.ev, S->stream);
     return e == hipSuccess;
 }
@@ -418,6 +490,10 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void **>(&S->buf[i].h_counts), sizeof(uint32_t) * 2 * S->cap,
                               hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->buf[i].d_dims), sizeof(BatchDims) * kDims);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&S->buf[i].h_dims), sizeof(BatchDims) * kDims,
+                              hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&S->buf[i].ev, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
@@ -425,6 +501,8 @@ svf_status svf_server_start(svf_ctx *ctx, const svf_server_cfg *cfg)
             if (b.d) hipFree(b.d);
             if (b.h) hipHostFree(b.h);
             if (b.h_counts) hipHostFree(b.h_counts);
+            if (b.d_dims) hipFree(b.d_dims);
+            if (b.h_dims) hipHostFree(b.h_dims);
             if (b.ev) hipEventDestroy(b.ev);
         }
         if (S->d_counts) hipFree(S->d_counts);
@@ -580,6 +658,10 @@ svf_status svf_server_stop(svf_ctx *ctx)
         hipFree(b.d);
         hipHostFree(b.h);
         hipHostFree(b.h_counts);
+        hipFree(b.d_dims);
+        hipHostFree(b.h_dims);
+        for (auto &g : b.graphs) hipGraphExecDestroy(g.second);
+        for (auto g : b.graph_defs) hipGraphDestroy(g);
         hipEventDestroy(b.ev);
     }
     hipFree(S->d_counts);

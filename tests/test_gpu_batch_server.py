@@ -114,11 +114,12 @@ def test_batch_matches_single_and_oracle(ctx, cases, use_graph):
         assert rel_err(outs[i].cpu().numpy(), ref) <= 1e-5
 
 
-def _server(ctx, budget=8 << 30, inflight=8):
+def _server(ctx, budget=8 << 30, inflight=8, use_graph=1):
     cfg = P.svf_server_cfg()
     cfg.max_inflight = inflight
     cfg.queue_capacity = 64
     cfg.hbm_budget_bytes = budget
+    cfg.use_graph = use_graph
     cfg.opts = P.default_opts()
     ctx.check(P.lib().svf_server_start(ctx.ptr, C.byref(cfg)))
 
@@ -142,9 +143,9 @@ def _wait(ctx, rid):
 
 
 def test_server_mix_equals_alone(ctx, cases):
-    # alone: one request at a time through the server
+    # alone: one request at a time through the server, steps launched kernel by kernel
     alone = []
-    _server(ctx)
+    _server(ctx, use_graph=0)
     try:
         for c in cases:
             out = torch.zeros(c[3].shape, dtype=torch.float32, device=DEV)
@@ -152,8 +153,9 @@ def test_server_mix_equals_alone(ctx, cases):
             alone.append(out.cpu().numpy())
     finally:
         P.lib().svf_server_stop(ctx.ptr)
-    # mix: everything submitted at once, twice over (requests join while others run)
-    _server(ctx, inflight=4)
+    # mix: everything submitted at once, twice over (requests join while others run);
+    # steps replayed from captured graphs
+    _server(ctx, inflight=4, use_graph=1)
     try:
         outs = [torch.zeros(c[3].shape, dtype=torch.float32, device=DEV) for c in cases + cases]
         ids = [_submit(ctx, c[3], c[4], c[2], outs[i]) for i, c in enumerate(cases + cases)]
@@ -220,6 +222,7 @@ def _srv_cfg(budget, inflight=1, queue=64):
     cfg.queue_capacity = queue
     cfg.hbm_budget_bytes = budget
     cfg.step_mpixels = 1   # one pass per step
+    cfg.use_graph = 1
     cfg.opts = P.default_opts()
     return cfg
 

@@ -144,6 +144,7 @@ def test_boundary_batch_and_server(ctx):
     cfg.max_inflight = 4
     cfg.queue_capacity = 16
     cfg.hbm_budget_bytes = 1 << 30
+    cfg.use_graph = 1
     cfg.opts = P.default_opts(boundary=b)
     P.svf_server_start(ctx, cfg)
     try:

@@ -100,6 +100,7 @@ def test_batch_and_server_mark_overflow(ctx):
     cfg.max_inflight = 4
     cfg.queue_capacity = 16
     cfg.hbm_budget_bytes = 1 << 30
+    cfg.use_graph = 1
     cfg.opts = o
     P.svf_server_start(ctx, cfg)
     try:

@@ -129,6 +129,7 @@ def test_batch_and_server_with_table(ctx):
     cfg.max_inflight = 4
     cfg.queue_capacity = 16
     cfg.hbm_budget_bytes = 1 << 30
+    cfg.use_graph = 1
     cfg.opts = P.default_opts(scale_map=P.SVF_SCALE_LUT)
     P.svf_server_start(ctx, cfg)
     try:
