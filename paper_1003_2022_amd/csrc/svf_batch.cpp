@@ -93,7 +93,9 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     // ---- checks and per-image plans ----
     std::vector<Plan> plans(n);
     int max_order = 0;
+    int kind_all = -1;   // the field kind shared by every image (-1: a mix)
     for (int i = 0; i < n; ++i) {
+        kind_all = i == 0 ? fields[i].kind : (fields[i].kind == kind_all ? kind_all : -1);
         svf_status st = check_image(ctx, &in[i], "in[i]", false);
         if (st) return st;
         st = check_image(ctx, &out[i], "out[i]", true);
@@ -233,7 +235,7 @@ extern "C" svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in,
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t r = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(fill_bytes / 4), s);
         if (r != hipSuccess) return r;
-        r = launch_scale_map_batch(B->d_jobs, counts[0], tot_smap, kPersistentScale, lutj.lut != nullptr, s);
+        r = launch_scale_map_batch(B->d_jobs, counts[0], tot_smap, kPersistentScale, lutj.lut != nullptr, kind_all, s);
         if (r != hipSuccess) return r;
         r = launch_fd_plan_batch(B->d_jobs, counts[0], tot_plan, s);
         if (r != hipSuccess) return r;

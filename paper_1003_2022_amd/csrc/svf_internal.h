@@ -163,8 +163,10 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
 // (persistent: `grid` work-groups loop over the work list).  With dims != nullptr the
 // kernels read n and the total from it instead (device memory) and the grid is
 // `grid` as given (a graph replayed for steps of different sizes).
-hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s,
-                                  const BatchDims *dims = nullptr);
+// kind: the field kind of every job of the table (a kernel compiled for it), or -1
+// for a mix
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, int kind,
+                                  hipStream_t s, const BatchDims *dims = nullptr);
 hipError_t launch_preint_batch(const Job *jobs, int n, int total_tiles, int grid, int preint, hipStream_t s,
                                const BatchDims *dims = nullptr);
 hipError_t launch_fd_batch(const Job *jobs, int n, int total_blocks, int grid, int preint, int fd_fp32, int nch,

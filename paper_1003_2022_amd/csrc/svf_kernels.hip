@@ -64,11 +64,66 @@ __device__ __forceinline__ void kurt_d(const double *pb, double t, double &d1, d
     d2 = 16.0 * (A + B) - 8.0 * s13 * s24;
 }
 
+// The minimiser's equation (Sec. 3.2.2): zeta'(t) = 32 t^3 + z2 t^2 + z3 t + z4 = 0 with
+// the coefficients taken from the particular solution pb.  zeta'' >= 8 sum p^2 > 0, so
+// zeta' is strictly increasing and, with t = x - b, b = z2 / 96, zeta' / 32 is the
+// depressed cubic x^3 + P x + Q with P > 0 (P = zeta''(-b) / 32) and one real root.
+struct Cubic {
+    double b, P, Q;
+};
+
+__device__ __forceinline__ Cubic zeta_cubic(const double *pb)
+{
+    const double p1 = pb[0], p2 = pb[1], p3 = pb[2], p4 = pb[3];
+    const double s13 = p1 + p3, s24 = p2 + p4;
+    const double z2 = 24.0 * (s13 - s24);
+    const double z3 = 16.0 * (p1 * p1 + p2 * p2 + p3 * p3 + p4 * p4) - 8.0 * s13 * s24;
+    const double z4 = 4.0 * (p1 * p1 * p1 - p2 * p2 * p2 + p3 * p3 * p3 - p4 * p4 * p4) +
+                      2.0 * s13 * (p2 * p2 + p4 * p4) - 2.0 * s24 * (p1 * p1 + p3 * p3);
+    Cubic c;
+    c.b = z2 * (1.0 / 96.0);
+    const double e3 = z3 * (1.0 / 32.0);
+    c.P = e3 - 3.0 * c.b * c.b;
+    c.Q = c.b * (2.0 * c.b * c.b - e3) + z4 * (1.0 / 32.0);
+    return c;
+}
+
+// Its root t: Cardano's formula with the larger cube root taken first (the two
+// terms of u have one sign, so nothing cancels), at the hardware estimates' ~1e-7
+// and a binary32 cube root, x0 within ~1e-6 of the scale; two Newton steps on the
+// depressed cubic (error e -> K e^2 + 1e-7 e, K <= 0.9 / sqrt(P)), which as written
+// resolve the root only to ~1e-11 of the scale where P is small (P, Q come from
+// cancelling sums); and a last Newton step on zeta' evaluated from the shifted
+// components (kurt_d), accurate to ~1e-16 of the scale.  `last` is that step, for
+// the caller's convergence check.
+__device__ __forceinline__ double cubic_root(const double *pb, const Cubic &c, double &last)
+{
+    const double D = 0.25 * c.Q * c.Q + c.P * c.P * c.P * (1.0 / 27.0);   // > 0
+    const double sD = D > 0.0 ? D * __builtin_amdgcn_rsq(D) : 0.0;
+    const double u = -0.5 * c.Q - copysign(sD, c.Q);
+    const float au = (float)fabs(u);
+    const double A = copysign((double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(au) * (1.0f / 3.0f)), u);
+    double x = au > 0.0f ? A - c.P * (1.0 / 3.0) * __builtin_amdgcn_rcp(A) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double x2 = x * x;
+        const double f = fma(x, x2 + c.P, c.Q), fp = fma(3.0, x2, c.P);
+        x -= f * __builtin_amdgcn_rcp(fp);
+    }
+    const double t = x - c.b;
+    double d1, d2;
+    kurt_d(pb, t, d1, d2);
+    last = d1 * __builtin_amdgcn_rcp(d2);
+    return t - last;
+}
+
 // Covariance (whole filter) -> scales, floor eps on a^2.  The feasible set of
-// M p = c, p >= eps is p = pbar + t e, t in [lo, hi]; ||K||^2 is strictly convex in t
-// (second derivative >= 8 sum p^2 > 0), so the minimiser is an end point or the one
-// root of the derivative, found by Newton steps kept inside a shrinking bracket.
-// The scales are stored in binary32, so the root is resolved to ~1e-13 relative.
+// M p = c, p >= eps is p = pbar + t e, t in [lo, hi]; ||K||^2 is strictly convex in t,
+// so its minimiser over the interval is the root of zeta' clamped to [lo, hi].  The
+// scales are stored in binary32; the root is resolved to ~1e-16 of the scale.  A
+// root whose last Newton step was not small (never seen; kept for safety: a NaN,
+// or P rounded to ~0) is redone by Newton steps inside a shrinking bracket, from
+// the derivative evaluated on the shifted components.
 __device__ void solve_feasible(double C11, double C12, double C22, double eps, double *a, bool &eps_act)
 {
     double pb[4];
@@ -79,16 +134,15 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
     double lo = fmax(eps - pb[0], eps - pb[2]);
     double hi = fmin(pb[1] - eps, pb[3] - eps);
     if (lo > hi) { const double m = 0.5 * (lo + hi); lo = hi = m; }
-    double t, dlo, dhi, dd;
-    kurt_d(pb, lo, dlo, dd);
-    kurt_d(pb, hi, dhi, dd);
-    if (dlo >= 0.0) {
-        t = lo;
-    } else if (dhi <= 0.0) {
-        t = hi;
+    const double scale = fmax(fmax(fabs(pb[0]), fabs(pb[1])), fmax(fabs(pb[2]), 1.0));
+    const Cubic cb = zeta_cubic(pb);
+    double last;
+    double t = cubic_root(pb, cb, last);
+    if (fabs(last) <= 1e-9 * scale) {
+        t = fmin(fmax(t, lo), hi);
     } else {
-        const double tol = 1e-13 * fmax(fmax(fabs(pb[0]), fabs(pb[1])), fmax(fabs(pb[2]), 1.0));
-        t = lo + (hi - lo) * div_pos(-dlo, dhi - dlo);
+        const double tol = 1e-13 * scale;
+        t = 0.5 * (lo + hi);
         for (int it = 0; it < 60; ++it) {
             double d1, d2;
             kurt_d(pb, t, d1, d2);
@@ -157,46 +211,60 @@ __device__ __forceinline__ void sincos_red(double th, double *sn, double *cs)
 
 // Largest feasible elongation at size s, orientation th: both diagonal-dominance
 // conditions C11 - |C12| >= eps/6, C22 - |C12| >= eps/6 written as linear
-// inequalities in rho (multiply by (1 + rho) / s).
-__device__ __forceinline__ double rho_limit(double s, double c, double sn, double eps)
+// inequalities in rho (multiply by 6 (1 + rho) s).  Returns rho if it satisfies
+// both (the usual case, no division), else the limit.
+__device__ __forceinline__ double rho_feasible(double rho, double s, double c, double sn, double eps)
 {
-    const double cs = fabs(c * sn), e = div_pos(eps, 6.0 * s);
+    const double s6 = 6.0 * s, cs = fabs(c * sn);
+    const double k1 = fma(s6, c * c - cs, -eps), k2 = fma(s6, sn * sn - cs, -eps);
+    const double n1 = fma(s6, sn * sn + cs, -eps), n2 = fma(s6, c * c + cs, -eps);
+    if (!((k1 < 0.0 && rho * -k1 > n1) || (k2 < 0.0 && rho * -k2 > n2))) return rho;
     double lim = INFINITY;
-    const double k1 = c * c - cs - e, k2 = sn * sn - cs - e;
-    if (k1 < 0.0) lim = fmin(lim, div_pos(sn * sn + cs - e, -k1));
-    if (k2 < 0.0) lim = fmin(lim, div_pos(c * c + cs - e, -k2));
+    if (k1 < 0.0) lim = fmin(lim, div_pos(n1, -k1));
+    if (k2 < 0.0) lim = fmin(lim, div_pos(n2, -k2));
     return lim;
+}
+
+// (sigma, rho, theta) request -> covariance, after the clamp of s and rho into the
+// feasible set (Sec. 3.2.2).
+__device__ __forceinline__ void srt_clamp(double sigma, double rho, double th, double eps, double &C11, double &C12,
+                                          double &C22, bool &clamped)
+{
+    double s = 2.0 * sigma * sigma;
+    clamped = false;
+    if (s < eps * (1.0 / 3.0)) { s = eps * (1.0 / 3.0); rho = 1.0; clamped = true; }
+    double sn, c;
+    sincos_red(th, &sn, &c);
+    const double lim = rho_feasible(rho, s, c, sn, eps);
+    if (lim != rho) { rho = lim * (1.0 - 1e-12); clamped = true; }
+    rho = fmax(rho, 1.0);
+    const double lmin = div_pos(s, 1.0 + rho), dl = lmin * (rho - 1.0);   // lambda_max - lambda_min
+    C11 = lmin + dl * c * c;
+    C12 = dl * c * sn;
+    C22 = lmin + dl * sn * sn;
 }
 
 __device__ void solve_srt(double sigma, double rho, double th, double eps, double *a, bool &clamped,
                           bool &eps_act)
 {
-    double s = 2.0 * sigma * sigma;
-    clamped = false;
-    if (s < eps / 3.0) { s = eps / 3.0; rho = 1.0; clamped = true; }
-    double sn, c;
-    sincos_red(th, &sn, &c);
-    const double lim = rho_limit(s, c, sn, eps);
-    if (rho > lim) { rho = lim * (1.0 - 1e-12); clamped = true; }
-    rho = fmax(rho, 1.0);
-    const double lmin = div_pos(s, 1.0 + rho), dl = lmin * (rho - 1.0);   // lambda_max - lambda_min
-    solve_feasible(lmin + dl * c * c, dl * c * sn, lmin + dl * sn * sn, eps, a, eps_act);
+    double C11, C12, C22;
+    srt_clamp(sigma, rho, th, eps, C11, C12, C22, clamped);
+    solve_feasible(C11, C12, C22, eps, a, eps_act);
 }
 
 __device__ bool solve_cov(double C11, double C12, double C22, double eps, double *a, bool &clamped, bool &eps_act)
 {
     if (!(isfinite(C11) && isfinite(C12) && isfinite(C22))) return false;
     if (!(C11 > 0.0 && C22 > 0.0 && C11 * C22 - C12 * C12 > 0.0)) return false;
-    if (C11 - fabs(C12) >= eps / 6.0 && C22 - fabs(C12) >= eps / 6.0) {
-        clamped = false;
-        solve_feasible(C11, C12, C22, eps, a, eps_act);
-        return true;
+    clamped = false;
+    if (!(C11 - fabs(C12) >= eps * (1.0 / 6.0) && C22 - fabs(C12) >= eps * (1.0 / 6.0))) {
+        // eigen-structure of the request, then the clamp of the (sigma, rho, theta) entry
+        const double s = C11 + C22, d = sqrt((C11 - C22) * (C11 - C22) + 4.0 * C12 * C12);
+        const double lmax = 0.5 * (s + d), lmin = 0.5 * (s - d);
+        srt_clamp(sqrt(0.5 * s), lmax / lmin, 0.5 * atan2(2.0 * C12, C11 - C22), eps, C11, C12, C22, clamped);
+        clamped = true;
     }
-    // eigen-structure of the request, then the clamp of the (sigma, rho, theta) entry
-    const double s = C11 + C22, d = sqrt((C11 - C22) * (C11 - C22) + 4.0 * C12 * C12);
-    const double lmax = 0.5 * (s + d), lmin = 0.5 * (s - d);
-    solve_srt(sqrt(0.5 * s), lmax / lmin, 0.5 * atan2(2.0 * C12, C11 - C22), eps, a, clamped, eps_act);
-    clamped = true;
+    solve_feasible(C11, C12, C22, eps, a, eps_act);
     return true;
 }
 
@@ -238,7 +306,7 @@ __device__ void lut_scales(const Job &J, float s, double rho_d, double th_d, dou
     const float r = sqrtf(s);
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[(q + k) & 3] = (double)(r * v[q]);
-    // report: the two diagonal-dominance conditions at s = 1 (as rho_limit)
+    // report: the two diagonal-dominance conditions at s = 1 (as rho_feasible)
     float sn, c;
     sincosf(phi, &sn, &c);
     const float cs = fabsf(c * sn), e = (float)J.lut_eps / 6.0f;
@@ -281,10 +349,13 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// One block: 64 columns x (4 waves x kSmapRows) rows, inside one tile.
-template <bool LUT>
+// One block: 64 columns x (4 waves x kSmapRows) rows, inside one tile.  KIND fixes
+// the field kind at compile time (-1: read from the job), so that a launch carries
+// only its kind's solve and the registers that one needs.
+template <bool LUT, int KIND = -1>
 __device__ void scale_map_block(const Job &J, int lb)
 {
+    const int f_kind = KIND >= 0 ? KIND : J.f_kind;
     __shared__ float s_rx[4], s_ry[4];
     __shared__ uint32_t s_cnt[4][4];
     const int rows_per_block = 4 * kSmapRows;
@@ -294,11 +365,13 @@ __device__ void scale_map_block(const Job &J, int lb)
     const int64_t c = (int64_t)bx * kSmapCols + lane;
     float rx = 0.f, ry = 0.f;
     uint32_t ncl = 0, nea = 0, nbad = 0, novf = 0;
-    // table lookup: the pixels' field entries are loaded up front (one 12-byte
-    // access each), so the four rows' memory latencies overlap
+    // the pixels' field entries are loaded up front (one 12-byte access each), so
+    // the four rows' memory latencies overlap (table lookup, and a solve of a
+    // kind fixed at compile time, whose rows are unrolled)
+    constexpr bool kPre = LUT || KIND == kSrt3 || KIND == kCov3;
     FieldEntry pf[kSmapRows];
-    if constexpr (LUT) {
-        if (J.f_kind != kScales4) {
+    if constexpr (kPre) {
+        if (f_kind != kScales4) {
 #pragma unroll
             for (int k = 0; k < kSmapRows; ++k) {
                 const int64_t r = (int64_t)by * rows_per_block + wave * kSmapRows + k;
@@ -312,18 +385,18 @@ __device__ void scale_map_block(const Job &J, int lb)
         double a[4];
         bool cl = false, ea = false, bad = false;
         const float *fv = J.field + r * J.f_rs;
-        if (J.f_kind == kScales4) {
+        if (f_kind == kScales4) {
             const float4 v = *reinterpret_cast<const float4 *>(fv + c * 4);
             a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
             bad = !(a[0] > 0.0 && a[1] > 0.0 && a[2] > 0.0 && a[3] > 0.0 && isfinite(a[0] + a[1] + a[2] + a[3]));
         } else {
             float f0, f1, f2;
-            if constexpr (LUT) {
+            if constexpr (kPre) {
                 f0 = pf[k].x; f1 = pf[k].y; f2 = pf[k].z;
             } else {
                 f0 = fv[c * 3]; f1 = fv[c * 3 + 1]; f2 = fv[c * 3 + 2];
             }
-            if (J.f_kind == kSrt3) {
+            if (f_kind == kSrt3) {
                 bad = !(isfinite(f0) && isfinite(f1) && isfinite(f2) && f0 > 0.f && f1 >= 1.f);
                 if (!bad) {
                     if (LUT) lut_scales(J, 2.0f * f0 * f0, (double)f1, (double)f2, a, cl, ea);
@@ -358,7 +431,7 @@ __device__ void scale_map_block(const Job &J, int lb)
         nea += ea;
         nbad += bad;
     };
-    if constexpr (LUT) {
+    if constexpr (kPre) {
 #pragma unroll
         for (int k = 0; k < kSmapRows; ++k) pixel(k);
     } else {
@@ -402,13 +475,13 @@ __device__ void scale_map_block(const Job &J, int lb)
     __syncthreads();   // the shared records are reused by the next block of a persistent loop
 }
 
-// The solve: occupancy 4 (<= 128 VGPRs, a few spilled), measured faster than 3
-// without spills or 5.  The table lookup is light and keeps the default.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map(Job J)
+// The solve, one kernel per field kind.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_scale_map(Job J)
 {
     // blocks of 16 pixel rows; the launch starts at the first row of tile row tr0
     const int nbx = (int)((J.W + kSmapCols - 1) / kSmapCols);
-    scale_map_block<false>(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
+    scale_map_block<false, KIND>(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
 }
 
 __global__ __launch_bounds__(256) void k_scale_map_lut(Job J)
@@ -417,8 +490,10 @@ __global__ __launch_bounds__(256) void k_scale_map_lut(Job J)
     scale_map_block<true>(J, blockIdx.x + J.tr0 * (J.T / (4 * kSmapRows)) * nbx);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_scale_map_batch(const Job *jobs, int n, int total,
-                                                                                                    const BatchDims *dims)
+// Batched solve: KIND is the one field kind of all the jobs, or -1 for a mix (every
+// kind's code in one kernel, with the registers of the largest).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_scale_map_batch(const Job *jobs, int n, int total, const BatchDims *dims)
 {
     if (dims) {
         n = dims->n;
@@ -427,7 +502,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
         const Job &J = jobs[j];
-        scale_map_block<false>(J, b - J.smap_base);
+        scale_map_block<false, KIND>(J, b - J.smap_base);
     }
 }
 
@@ -1059,7 +1134,9 @@ hipError_t launch_scale_map(const Job &j, hipStream_t s)
     if (r1 <= r0) return hipSuccess;
     const int nb = scale_map_blocks(r1 - r0, j.W);
     if (j.lut) hipLaunchKernelGGL(k_scale_map_lut, dim3(nb), dim3(256), 0, s, j);
-    else hipLaunchKernelGGL(k_scale_map, dim3(nb), dim3(256), 0, s, j);
+    else if (j.f_kind == kSrt3) hipLaunchKernelGGL(k_scale_map<kSrt3>, dim3(nb), dim3(256), 0, s, j);
+    else if (j.f_kind == kCov3) hipLaunchKernelGGL(k_scale_map<kCov3>, dim3(nb), dim3(256), 0, s, j);
+    else hipLaunchKernelGGL(k_scale_map<kScales4>, dim3(nb), dim3(256), 0, s, j);
     return hipGetLastError();
 }
 
@@ -1128,8 +1205,8 @@ hipError_t launch_preint_window(const Job &j, int channel, int64_t r0, int64_t c
     return hipGetLastError();
 }
 
-hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, hipStream_t s,
-                                  const BatchDims *dims)
+hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int grid, bool lut, int kind,
+                                  hipStream_t s, const BatchDims *dims)
 {
     if (!dims) {
         if (total_blocks == 0) return hipSuccess;
@@ -1137,7 +1214,11 @@ hipError_t launch_scale_map_batch(const Job *jobs, int n, int total_blocks, int 
     }
     grid = std::max(1, grid);
     if (lut) hipLaunchKernelGGL(k_scale_map_batch_lut, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
-    else hipLaunchKernelGGL(k_scale_map_batch, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
+    else if (kind == kSrt3) hipLaunchKernelGGL(k_scale_map_batch<kSrt3>, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
+    else if (kind == kCov3) hipLaunchKernelGGL(k_scale_map_batch<kCov3>, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
+    else if (kind == kScales4)
+        hipLaunchKernelGGL(k_scale_map_batch<kScales4>, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
+    else hipLaunchKernelGGL(k_scale_map_batch<-1>, dim3(grid), dim3(256), 0, s, jobs, n, total_blocks, dims);
     return hipGetLastError();
 }
 

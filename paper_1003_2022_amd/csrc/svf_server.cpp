@@ -165,7 +165,7 @@ int grid_of(int64_t work, int cap)
 }
 
 // Launch one step from the tables in `b`; returns false on a HIP error.
-bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, int tot_plan, const int *counts,
+bool launch_step(Server *S, StepBuf &b, int nsmap, int smap_kind, int tot_smap, int tot_plan, const int *counts,
                  const int *tot_tiles, const int *tot_blk)
 {
     BatchDims *h = b.h_dims;
@@ -179,7 +179,8 @@ bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, int tot_plan, c
     const int g_fill = grid_of(nsmap, 64), g_smap = grid_of(tot_smap, kPersistentScale);
     const int g_plan = grid_of((tot_plan + 255) / 256, 256);
     int g_pre[kMaxChannels + 1] = {}, g_fd[kMaxChannels + 1] = {};
-    std::string key = nsmap ? "s" + std::to_string(g_fill) + "," + std::to_string(g_smap) + "," + std::to_string(g_plan)
+    std::string key = nsmap ? "s" + std::to_string(g_fill) + "," + std::to_string(g_smap) + "," +
+                                  std::to_string(g_plan) + "," + std::to_string(smap_kind)
                             : std::string("-");
     for (int ch = 1; ch <= kMaxChannels; ++ch) {
         if (!counts[ch]) continue;
@@ -193,7 +194,7 @@ bool launch_step(Server *S, StepBuf &b, int nsmap, int tot_smap, int tot_plan, c
         // the tile records and counters of the newly admitted requests start at zero
         if (e == hipSuccess && nsmap) e = launch_fill_jobs(b.d, nsmap, g_fill, st, d + 0);
         if (e == hipSuccess && nsmap)
-            e = launch_scale_map_batch(b.d, nsmap, tot_smap, g_smap, S->lut != nullptr, st, d + 0);
+            e = launch_scale_map_batch(b.d, nsmap, tot_smap, g_smap, S->lut != nullptr, smap_kind, st, d + 0);
         if (e == hipSuccess && nsmap) e = launch_fd_plan_batch(b.d, nsmap, tot_plan, st, d + 1, g_plan);
         for (int ch = 1; ch <= kMaxChannels && e == hipSuccess; ++ch)
             if (counts[ch])
@@ -371,7 +372,7 @@ void loop(Server *S)
         // ---- build the tables (only this thread writes q.pass / q.off) ----
         int counts[kTables] = {}, tot_tiles[kTables] = {}, tot_blk[kTables] = {};
         int tot_smap = 0, tot_plan = 0;
-        int nsmap = 0;
+        int nsmap = 0, smap_kind = -1;   // the field kind shared by the new requests (-1: a mix)
         for (auto &pr : running) {
             const uint64_t id = pr.first;
             Req &q = *pr.second;
@@ -396,6 +397,7 @@ void loop(Server *S)
                 js.blk_base = tot_plan;   // the scale-map table also drives the block plan
                 js.req_counts = S->d_counts + 2 * q.slot;
                 tot_plan += fd_blocks_job(js);
+                smap_kind = nsmap == 0 ? js.f_kind : (js.f_kind == smap_kind ? smap_kind : -1);
                 b.h[nsmap++] = js;
             }
             Job jp = base;
@@ -414,7 +416,7 @@ void loop(Server *S)
             if (q.pass == q.r.order) b.finishing.push_back(id);
             b.running.push_back(id);
         }
-        if (!launch_step(S, b, nsmap, tot_smap, tot_plan, counts, tot_tiles, tot_blk)) {
+        if (!launch_step(S, b, nsmap, smap_kind, tot_smap, tot_plan, counts, tot_tiles, tot_blk)) {
             // nothing more runs for the requests in flight: wait for whatever did reach
             // the device, then end them all with SVF_EHIP and give their memory back
             hipStreamSynchronize(S->stream);
