@@ -25,6 +25,12 @@ elliptical filtering using box splines"):
   structure tensor J = w * (g g^T), the triple (s*, rho*, theta*) from its
   eigen-decomposition (numpy.linalg.eigh) by the printed rules, and the filter
   driven by it.
+* ``boxspline_m``, ``zp_m``, ``pass_single``, ``filter_single`` -- the iterated box
+  spline beta^{4,m}_a (Sec. 2.3, eq. (iterated_spline) / (conv2)) evaluated exactly
+  (a B-spline convolution integrated cell by cell) and one single pass with it: the
+  direct sum, or m-fold running sums with (m+1)^4 differences and ZP^{*m}
+  interpolation (a reading of Sec. 3.3: the paper applies the iterated spline by m
+  passes, and this is the single-pass form of the same kernel).
 * ``lut_table``, ``scales_lut``, ``filter_lut`` -- the look-up-table scale map
   of Sec. 3.2.2 (unit-size solutions over elongation and one octant, O1/O2).
 * ``boundary`` (all) -- what each pass reads outside the image: zero, the
@@ -102,6 +108,19 @@ def lib():
         L.svfo_table1_tap.argtypes = [dp, C.c_int, dp, dp, dp]
         L.svfo_tau.restype = None
         L.svfo_tau.argtypes = [dp, dp, dp]
+        L.svfo_boxspline_m.restype = C.c_double
+        L.svfo_boxspline_m.argtypes = [dp, C.c_int, C.c_double, C.c_double]
+        L.svfo_zp_m.restype = C.c_double
+        L.svfo_zp_m.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.svfo_pass_fast_m.restype = C.c_int
+        L.svfo_pass_fast_m.argtypes = [vp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_long, dp, C.c_long, C.c_long,
+                                       C.c_long, C.c_long, C.c_int, dp]
+        L.svfo_pass_brute_m.restype = C.c_int
+        L.svfo_pass_brute_m.argtypes = [vp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_long, dp, C.c_long, C.c_long,
+                                        C.c_long, C.c_long, C.c_int, dp]
+        L.svfo_preint_window_m_f64.restype = None
+        L.svfo_preint_window_m_f64.argtypes = [vp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_long, C.c_long,
+                                               C.c_long, C.c_long, C.c_long, C.c_int, dp]
         L.svfo_set_threads.restype = C.c_int
         L.svfo_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -146,6 +165,17 @@ def boxspline_grid(a, x0: float, y0: float, h: float, nx: int, ny: int, hy: floa
     out = np.empty((ny, nx), dtype=np.float64)
     lib().svfo_boxspline_grid(_dp(av), x0, y0, h, h if hy is None else hy, nx, ny, _dp(out))
     return out
+
+
+def boxspline_m(a, m: int, x: float, y: float) -> float:
+    """beta^{4,m}_a(x, y): the m-fold self-convolution of beta^4_a (eq. (iterated_spline))."""
+    av = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return lib().svfo_boxspline_m(_dp(av), int(m), float(x), float(y))
+
+
+def zp_m(m: int, x: float, y: float) -> float:
+    """The m-fold self-convolution of the ZP element (beta^{4,m}_b, b = (1, sqrt2, 1, sqrt2))."""
+    return lib().svfo_zp_m(int(m), float(x), float(y))
 
 
 def table1_tap(a, i: int):
@@ -228,6 +258,15 @@ def preint_window_i64(img: np.ndarray, r0: int, c0: int, h: int, w: int) -> np.n
     H, W = img.shape
     g = np.empty((h, w), dtype=np.int64)
     lib().svfo_preint_window_i64(img.ctypes.data, H, W, r0, c0, h, w, g.ctypes.data)
+    return g
+
+
+def preint_window_m_f64(img: np.ndarray, r0: int, c0: int, h: int, w: int, m: int) -> np.ndarray:
+    """RS1..RS4 applied m times (sqrt2 factors each time) to img on a window."""
+    img = np.ascontiguousarray(img)
+    H, W = img.shape
+    g = np.empty((h, w), dtype=np.float64)
+    lib().svfo_preint_window_m_f64(img.ctypes.data, _img_code(img), 0, 0, H, W, r0, c0, h, w, int(m), _dp(g))
     return g
 
 
@@ -548,3 +587,38 @@ def filter_lut(img: np.ndarray, field: np.ndarray, kind: int, order: int = 1, no
         return np.stack([filter_scales(img[..., ch], a, order, method, tile, boundary) for ch in range(img.shape[2])],
                         -1)
     return filter_scales(img, a, order, method, tile, boundary)
+
+
+# ----------------------------------------------------------------------------- single pass with beta^{4,m}
+
+def pass_single(img: np.ndarray, a_rect: np.ndarray, m: int, method: str = "brute", r0: int = 0, c0: int = 0):
+    """One pass with the iterated box spline beta^{4,m}_{a(n)} over the output rectangle
+    (r0, c0) + a_rect.shape[:2] of img (zero outside): 'brute' is the direct sum
+    sum_k f[k] beta^{4,m}_{a(n)}(n - k), 'fast' the m-fold running sums with the
+    (m+1)^4-tap difference and ZP^{*m} interpolation on per-pixel windows."""
+    img = np.ascontiguousarray(img)
+    if img.dtype not in (np.float64, np.float32, np.uint16):
+        img = img.astype(np.float64)
+    fh, fw = img.shape
+    h, w = a_rect.shape[:2]
+    a_rect = np.ascontiguousarray(a_rect, dtype=np.float64)
+    out = np.empty((h, w), dtype=np.float64)
+    if h == 0 or w == 0:
+        return out
+    fn = {"brute": lib().svfo_pass_brute_m, "fast": lib().svfo_pass_fast_m}[method]
+    rc = fn(img.ctypes.data, _img_code(img), 0, 0, fh, fw, _dp(a_rect), r0, c0, h, w, int(m), _dp(out))
+    if rc != 0:
+        raise RuntimeError("oracle single pass failed")
+    return out
+
+
+def filter_single(img: np.ndarray, field: np.ndarray, kind: int, m: int, eps: float = DEFAULT_EPS,
+                  method: str = "brute"):
+    """Single-pass filter with beta^{4,m}_{a(n) / sqrt(m)} (the iterated spline of Sec. 3.3 with
+    the covariance of beta^4_{a(n)}: the scale solve of Sec. 3.2.2, then a / sqrt(m)), zero
+    outside the image; (H, W) or (H, W, C) images; returns float64."""
+    a, _ = scales(field, kind, m, eps)
+    if img.ndim == 3:
+        return np.stack([pass_single(img[..., ch], a, m, method) for ch in range(img.shape[2])], -1)
+    return pass_single(img, a, m, method)
+

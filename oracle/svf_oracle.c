@@ -30,6 +30,10 @@
  *      (parts 3 + 4 on windows that contain every sample a pixel reads) and the
  *      brute-force direct sum  out[n] = sum_k f[k] beta^4_{a(n)}(n - k)
  *      (eq. (discrete) with the Dirac-comb input model of Sec. 2.2.2).
+ *   6. The iterated box spline beta^{4,m}_a (Sec. 2.3, eq. (iterated_spline) and
+ *      eq. (conv2)) evaluated exactly, and one single-pass filter with it: the direct
+ *      sum, and the fast form (m-fold running sums, (m+1)^4 differences, interpolation
+ *      with the m-fold convolution of the ZP element).
  *
  * Coordinates: image f[row][col]; x = column index n1, y = row index n2.
  * Directions theta_k = (k-1) pi/4: u1 = (1,0), u2 = (1,1)/sqrt2, u3 = (0,1),
@@ -605,3 +609,274 @@ int svfo_set_threads(int n)
     if (n > 0) omp_set_num_threads(n);
     return omp_get_max_threads();
 }
+
+/* ------------------------------------------------------------------------- */
+/* 6. Iterated box spline beta^{4,m}_a and the single-pass filter             */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * beta^{4,m}_a is the m-fold convolution of beta^4_a with itself (eq. (iterated_spline)):
+ * the density of sum_k S_k a_k u_k with S_k the sum of m independent U(-1/2, 1/2), whose
+ * Fourier transform is prod_k sinc^m (eq. (conv2)).  S_k a_k has the density
+ * B_m(s / a_k) / a_k, B_m the centred cardinal B-spline of order m.  Pairing the
+ * directions, X = S1 a1 u1 + S3 a3 u3 has the density B_m(x/a1) B_m(y/a3) / (a1 a3) and
+ * Y = S2 a2 u2 + S4 a4 u4 the same in the rotated coordinates (u2.z, u4.z), and
+ *   beta^{4,m}_a(x) = int p_X(x - z) p_Y(z) dz.
+ * Each factor is one polynomial on each cell of an m x m grid (p_Y's grid in the rotated
+ * frame), so the integral is a sum over the convex intersections of one cell of each.
+ * On an intersection the integrand is a polynomial of degree 4(m-1); it is integrated on
+ * the triangles of a fan by the collapsed (Duffy) product of n = 2m-1 point
+ * Gauss-Legendre rules, exact for that degree.
+ */
+
+/* Centred cardinal B-spline of order m (support [-m/2, m/2]) by its truncated powers. */
+static double bspline_c(int m, double x)
+{
+    double h = 0.5 * m;
+    if (x <= -h || x >= h) return 0.0;
+    double s = 0.0, c = 1.0, fact = 1.0;
+    for (int j = 2; j < m; ++j) fact *= j;
+    for (int j = 0; j <= m; ++j) {
+        double t = x + h - j;
+        if (t > 0.0) {
+            double p = 1.0;
+            for (int e = 0; e < m - 1; ++e) p *= t;
+            s += c * p;
+        }
+        c = -c * (double)(m - j) / (double)(j + 1);
+    }
+    return s / fact;
+}
+
+/* n-point Gauss-Legendre nodes and weights on [0, 1] (Newton on the Legendre recurrence). */
+static void gauss01(int n, double *x, double *w)
+{
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double pn = n == 1 ? z : p1, pm = n == 1 ? 1.0 : p0;
+            dp = n * (z * pn - pm) / (z * z - 1.0);
+            double dz = pn / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-17) break;
+        }
+        x[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);   /* 2 / ((1 - z^2) P'^2), halved for [0, 1] */
+    }
+}
+
+struct itp {                 /* integrand of one evaluation */
+    const double *a;
+    int m;
+    double x1, x2;
+};
+
+static double itp_f(const struct itp *q, double z1, double z2)
+{
+    const double *a = q->a;
+    double s = (z1 + z2) * ISQ2, t = (z2 - z1) * ISQ2;
+    double px = bspline_c(q->m, (q->x1 - z1) / a[0]) * bspline_c(q->m, (q->x2 - z2) / a[2]) / (a[0] * a[2]);
+    if (px == 0.0) return 0.0;
+    return px * bspline_c(q->m, s / a[1]) * bspline_c(q->m, t / a[3]) / (a[1] * a[3]);
+}
+
+/* Integral over a convex polygon: fan triangles, collapsed Gauss product rule. */
+static double poly_integral(const struct itp *q, const double *px, const double *py, int n, int ng,
+                            const double *gx, const double *gw)
+{
+    double acc = 0.0;
+    for (int k = 1; k + 1 < n; ++k) {
+        double ax = px[0], ay = py[0];
+        double e1x = px[k] - ax, e1y = py[k] - ay, e2x = px[k + 1] - px[k], e2y = py[k + 1] - py[k];
+        double det = fabs(e1x * e2y - e1y * e2x);
+        if (det == 0.0) continue;
+        double tri = 0.0;
+        for (int i = 0; i < ng; ++i)
+            for (int j = 0; j < ng; ++j) {
+                double s = gx[i], t = gx[j];
+                double z1 = ax + s * e1x + s * t * e2x, z2 = ay + s * e1y + s * t * e2y;
+                tri += gw[i] * gw[j] * s * itp_f(q, z1, z2);
+            }
+        acc += det * tri;
+    }
+    return acc;
+}
+
+double svfo_boxspline_m(const double *a, int m, double x, double y)
+{
+    if (m < 1 || m > 4) return NAN;
+    double gx[8], gw[8];
+    int ng = 2 * m - 1;
+    gauss01(ng, gx, gw);
+    struct itp q = {a, m, x, y};
+    double h = 0.5 * m, acc = 0.0;
+    for (int i1 = 0; i1 < m; ++i1)
+        for (int i3 = 0; i3 < m; ++i3) {
+            /* cell of p_X(x - z): (x - z)/a1 in [i1 - h, i1 + 1 - h], same for row with a3 */
+            double z1lo = x - a[0] * (i1 + 1 - h), z1hi = x - a[0] * (i1 - h);
+            double z2lo = y - a[2] * (i3 + 1 - h), z2hi = y - a[2] * (i3 - h);
+            for (int i2 = 0; i2 < m; ++i2)
+                for (int i4 = 0; i4 < m; ++i4) {
+                    double s0 = a[1] * (i2 - h), s1 = a[1] * (i2 + 1 - h);
+                    double t0 = a[3] * (i4 - h), t1 = a[3] * (i4 + 1 - h);
+                    /* corners z = s u2 + t u4, counter-clockwise in (s, t) */
+                    double bx[16], by[16], cx[16], cy[16];
+                    double ss[4] = {s0, s1, s1, s0}, tt[4] = {t0, t0, t1, t1};
+                    for (int k = 0; k < 4; ++k) {
+                        bx[k] = (ss[k] - tt[k]) * ISQ2;
+                        by[k] = (ss[k] + tt[k]) * ISQ2;
+                    }
+                    int n = 4;
+                    n = clip_half(bx, by, n, -1.0, 0.0, -z1lo, cx, cy); if (n < 3) continue;
+                    n = clip_half(cx, cy, n, 1.0, 0.0, z1hi, bx, by);   if (n < 3) continue;
+                    n = clip_half(bx, by, n, 0.0, -1.0, -z2lo, cx, cy); if (n < 3) continue;
+                    n = clip_half(cx, cy, n, 0.0, 1.0, z2hi, bx, by);   if (n < 3) continue;
+                    acc += poly_integral(&q, bx, by, n, ng, gx, gw);
+                }
+        }
+    return acc;
+}
+
+/* beta^{4,m}_b, b = (1, sqrt2, 1, sqrt2): the m-fold convolution of the ZP element. */
+double svfo_zp_m(int m, double x, double y)
+{
+    const double b[4] = {1.0, SQ2, 1.0, SQ2};
+    return svfo_boxspline_m(b, m, x, y);
+}
+
+/*
+ * Fast single pass with beta^{4,m}_a.  beta^{4,m} is the box spline whose directions are
+ * those of beta^4 each taken m times; the same argument as for m = 1 (Sec. 3.1) gives
+ *   fbar[n] = (1 / prod_k a_k^m) sum_{j in {0..m}^4} prod_k C(m, j_k) (-1)^{j_k}
+ *             F_m(n + m tau - sum_k j_k a_k u_k),   F_m(y) = sum_l g_m[l] ZP^{*m}(y - l),
+ * where g_m applies the running sums RS1..RS4 m times (each time with the sqrt2 factors)
+ * and tau is the shift of Sec. 3.1 step (2).  (m = 1 is eq. (final_eqn).)  A reading: the
+ * paper states the iterated spline and its use by repeated passes (Sec. 3.3, "Higher-order
+ * box splines"), not this single-pass form; fast = direct sum is checked by the tests.
+ */
+double svfo_fd_pixel_m(const double *g, long wh, long ww, long wr0, long wc0, long n1, long n2, const double *a,
+                       int m)
+{
+    double t1, t2;
+    tau_of(a, &t1, &t2);
+    double w = 1.0;
+    for (int k = 0; k < 4; ++k)
+        for (int e = 0; e < m; ++e) w /= a[k];
+    double binom[5] = {1, 0, 0, 0, 0};
+    for (int j = 1; j <= m; ++j) binom[j] = binom[j - 1] * (double)(m - j + 1) / (double)j;
+    double ap2 = a[1] / SQ2, ap4 = a[3] / SQ2, reach = 1.5 * m, acc = 0.0;
+    int nt = 1;
+    for (int k = 0; k < 4; ++k) nt *= (m + 1);
+    for (int idx = 0; idx < nt; ++idx) {
+        int j[4], r = idx;
+        double coef = 1.0;
+        for (int k = 0; k < 4; ++k) {
+            j[k] = r % (m + 1);
+            r /= (m + 1);
+            coef *= ((j[k] & 1) ? -1.0 : 1.0) * binom[j[k]];
+        }
+        double x1 = j[0] * a[0] + j[1] * ap2 - j[3] * ap4;
+        double x2 = j[1] * ap2 + j[2] * a[2] + j[3] * ap4;
+        double y1 = (double)n1 + m * t1 - x1, y2 = (double)n2 + m * t2 - x2;
+        long c_lo = (long)floor(y1 - reach), c_hi = (long)ceil(y1 + reach);
+        long r_lo = (long)floor(y2 - reach), r_hi = (long)ceil(y2 + reach);
+        double F = 0.0;
+        for (long mr = r_lo; mr <= r_hi; ++mr)
+            for (long mc = c_lo; mc <= c_hi; ++mc) {
+                double z = svfo_zp_m(m, y1 - (double)mc, y2 - (double)mr);
+                if (z == 0.0) continue;
+                long rr = mr - wr0, cc = mc - wc0;
+                if (rr < 0 || cc < 0 || rr >= wh || cc >= ww) return NAN;
+                F += g[rr * ww + cc] * z;
+            }
+        acc += coef * w * F;
+    }
+    return acc;
+}
+
+/* g = (RS1..RS4 applied m times) of the window of the image (zero outside it). */
+void svfo_preint_window_m_f64(const void *img, int dtype, long fr0, long fc0, long fh, long fw, long r0, long c0,
+                              long h, long w, int m, double *g)
+{
+    svfo_preint_window_f64(img, dtype, fr0, fc0, fh, fw, r0, c0, h, w, g);
+    double *t = (double *)malloc((size_t)h * (size_t)w * sizeof(double));
+    for (int it = 1; it < m; ++it) {
+        memcpy(t, g, (size_t)h * (size_t)w * sizeof(double));
+        svfo_preint_f64(t, h, w, g);
+    }
+    free(t);
+}
+
+/* One single pass over a rectangle of outputs, per-pixel windows (the smallest window a
+ * pixel reads, which keeps the m-fold sums as small as they can be); fast form.  A
+ * window that starts inside the image is exact for the same reason as for m = 1: the
+ * truncation only adds terms that one direction's m-th difference removes. */
+int svfo_pass_fast_m(const void *f, int dtype, long fr0, long fc0, long fh, long fw, const double *a, long r0,
+                     long c0, long h, long w, int m, double *out)
+{
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail)
+    for (long i = 0; i < h * w; ++i) {
+        long r = r0 + i / w, c = c0 + i % w;
+        const double *ap = a + (size_t)i * 4;
+        /* every lattice sample the taps' interpolants read */
+        double t1, t2;
+        tau_of(ap, &t1, &t2);
+        double ap2 = ap[1] / SQ2, ap4 = ap[3] / SQ2, reach = 1.5 * m;
+        long wc_lo = c, wc_hi = c, wr_lo = r, wr_hi = r;
+        for (int j1 = 0; j1 <= m; ++j1)
+            for (int j2 = 0; j2 <= m; ++j2)
+                for (int j3 = 0; j3 <= m; ++j3)
+                    for (int j4 = 0; j4 <= m; ++j4) {
+                        double y1 = c + m * t1 - (j1 * ap[0] + j2 * ap2 - j4 * ap4);
+                        double y2 = r + m * t2 - (j2 * ap2 + j3 * ap[2] + j4 * ap4);
+                        long lo = (long)floor(y1 - reach), hi = (long)ceil(y1 + reach);
+                        if (lo < wc_lo) wc_lo = lo;
+                        if (hi > wc_hi) wc_hi = hi;
+                        lo = (long)floor(y2 - reach);
+                        hi = (long)ceil(y2 + reach);
+                        if (lo < wr_lo) wr_lo = lo;
+                        if (hi > wr_hi) wr_hi = hi;
+                    }
+        long wh = wr_hi - wr_lo + 1, ww = wc_hi - wc_lo + 1;
+        double *g = (double *)malloc((size_t)wh * (size_t)ww * sizeof(double));
+        svfo_preint_window_m_f64(f, dtype, fr0, fc0, fh, fw, wr_lo, wc_lo, wh, ww, m, g);
+        double v = svfo_fd_pixel_m(g, wh, ww, wr_lo, wc_lo, c, r, ap, m);
+        if (isnan(v)) fail = 1;
+        out[i] = v;
+        free(g);
+    }
+    return fail ? -1 : 0;
+}
+
+/* Direct sum, one single pass: out[n] = sum_k f[k] beta^{4,m}_{a(n)}(n - k). */
+int svfo_pass_brute_m(const void *f, int dtype, long fr0, long fc0, long fh, long fw, const double *a, long r0,
+                      long c0, long h, long w, int m, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < h * w; ++i) {
+        long r = r0 + i / w, c = c0 + i % w;
+        const double *ap = a + (size_t)i * 4;
+        double rx, ry;
+        svfo_support_halfwidths(ap, &rx, &ry);
+        long k1lo = (long)floor(c - m * rx), k1hi = (long)ceil(c + m * rx);
+        long k2lo = (long)floor(r - m * ry), k2hi = (long)ceil(r + m * ry);
+        double acc = 0.0;
+        for (long k2 = k2lo; k2 <= k2hi; ++k2)
+            for (long k1 = k1lo; k1 <= k1hi; ++k1) {
+                double fv = img_at(f, dtype, fr0, fc0, fh, fw, k2, k1);
+                if (fv == 0.0) continue;
+                acc += fv * svfo_boxspline_m(ap, m, (double)(c - k1), (double)(r - k2));
+            }
+        out[i] = acc;
+    }
+    return 0;
+}
+
