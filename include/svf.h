@@ -203,6 +203,34 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
                       const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep);
 
 /*
+ * One pass with the iterated box spline beta^{4,m} (Sec. 2.3, eq. (iterated_spline);
+ * Sec. 3.3, "Higher-order box splines"): per channel
+ *
+ *     out[n] = sum_k f[k] beta^{4,m}_{a(n)}(n - k),   a(n) = (scales of the field) / sqrt(m),
+ *
+ * the scales solved as for svf_filter of order m (floor m * opts.eps_px2), so that the
+ * covariance is the field's.  beta^{4,m} is beta^4 convolved with itself m times
+ * (Fourier transform prod_k sinc^m, eq. (conv2)); where svf_filter of order m applies
+ * m passes of beta^4 with the scales of each pass's own pixels, this applies the exact
+ * beta^{4,m} of each output pixel's scales.  m = 2.  Fast form: the running sums
+ * RS1..RS4 applied twice on a window per 16 x 16 tile, the 81-tap difference
+ * prod_k (1 - shift by a_k u_k)^2, interpolation with ZP*ZP.
+ * Precision: the doubled sums grow like the window side^8, so the outputs of small
+ * filters on busy images lose digits: a pixel whose rounding bound
+ * 2^-46 max|g2| / prod_k a_k^2 (max over its tile's window) exceeds 1e-6 of the window's
+ * largest input magnitude is written as NaN, as are the pixels of a tile whose window
+ * exceeds the 160 KiB of LDS (support half-width about 60 px) and pixels with invalid
+ * SVF_FIELD_SCALES4 scales.  With rep != NULL the call waits, fills *rep
+ * (overflow_px = NaN outputs, max_reach_px = largest beta^{4,2} support half-width) and
+ * returns SVF_ERANGE if some output is NaN, SVF_EINVAL for invalid field entries.  The
+ * call waits for the scale map in any case (the window size follows from it).
+ * SVF_EUNSUPPORTED: m != 2, opts.boundary other than zero, opts.preint other than
+ * SVF_PRE_F64, opts.fd_fp32, opts.bands > 1.  out must not alias in.
+ */
+svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const svf_field *field, int m,
+                             const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep);
+
+/*
  * svf_filter for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
  * arguments, checks and results as svf_filter (bit for bit: the same kernels),

@@ -101,6 +101,9 @@ def lib() -> C.CDLL:
     L.svf_preintegrate.restype = st
     L.svf_preintegrate.argtypes = [vp, P(svf_image), C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int, vp, vp]
     L.svf_filter.restype = st
+    L.svf_filter_single.restype = st
+    L.svf_filter_single.argtypes = [vp, P(svf_image), P(svf_field), C.c_int, P(svf_opts), P(svf_image), vp,
+                                    P(svf_report)]
     L.svf_filter.argtypes = [vp, P(svf_image), P(svf_field), C.c_int, C.c_int, P(svf_opts), P(svf_image), vp, P(svf_report)]
     L.svf_filter_batch.restype = st
     L.svf_filter_batch.argtypes = [vp, C.c_int, P(svf_image), P(svf_field), P(C.c_int), P(svf_opts), P(svf_image), vp, C.c_int]
@@ -258,6 +261,16 @@ def svf_filter(ctx: Context, img: svf_image, field: svf_field, N: int, order: in
     rep = svf_report() if report else None
     st = lib().svf_filter(ctx.ptr, C.byref(img), C.byref(field), N, order, C.byref(opts) if opts else None,
                           C.byref(out), _stream_handle(stream), C.byref(rep) if rep is not None else None)
+    if report:
+        return st, rep
+    return ctx.check(st)
+
+
+def svf_filter_single(ctx: Context, img: svf_image, field: svf_field, m: int, opts: svf_opts | None,
+                      out: svf_image, stream=None, report: bool = False):
+    rep = svf_report() if report else None
+    st = lib().svf_filter_single(ctx.ptr, C.byref(img), C.byref(field), m, C.byref(opts) if opts else None,
+                                 C.byref(out), _stream_handle(stream), C.byref(rep) if rep is not None else None)
     if report:
         return st, rep
     return ctx.check(st)

@@ -11,7 +11,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libsvf.so"
 SOURCES = ["svf_kernels.hip", "svf_fd.hip", "svf_st.hip", "svf_runtime.cpp", "svf_batch.cpp", "svf_server.cpp", "svf_st.cpp",
-           "svf_noalloc.hip"]
+           "svf_noalloc.hip", "svf_single.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

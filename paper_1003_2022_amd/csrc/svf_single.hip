@@ -1,0 +1,354 @@
+// svf_single.hip -- one pass with the iterated box spline beta^{4,2} (Sec. 2.3,
+// eq. (iterated_spline); Sec. 3.3): out[n] = sum_k f[k] beta^{4,2}_{a(n)}(n - k).
+//
+// beta^{4,2}_a is the box spline whose four directions a_k u_k are each taken twice.
+// The argument of Sec. 3.1 carries over: with g2 = the running sums RS1..RS4 applied
+// twice (sqrt2 factors each time), the filter is the 81-tap difference
+//
+//   out[n] = (1 / prod_k a_k^2) sum_{j in {0,1,2}^4} prod_k C(2, j_k) (-1)^{j_k}
+//            F2(n + 2 tau - sum_k j_k a_k u_k),      F2(y) = sum_l g2[l] (ZP*ZP)(y - l),
+//
+// tau the shift of Sec. 3.1 step (2).  ZP*ZP is a piecewise polynomial of degree 6 on
+// the four-direction mesh; its 36 weights at a fractional position come from a table
+// of polynomials on one mesh triangle (svf_zp2_table.h), the other three triangles of
+// the unit square mapping onto it by the square's quarter turns.
+//
+// One work-group per 16 x 16 output tile and channel: the tile's window (every lattice
+// sample its 256 pixels' taps read) is loaded into LDS as binary64, summed twice in
+// place (RS1 along the rows, then RS2, RS3, RS4 in one top-to-bottom sweep of the rows
+// with one barrier per row), and each thread evaluates its pixel's 81 taps from LDS.
+//
+// Precision: the doubled sums grow like the window side^8, and the difference cancels
+// all but ~prod a_k^2 of that.  A pixel whose rounding bound 2^-46 max|g2| / prod a_k^2
+// exceeds 1e-6 of the window's largest input magnitude is written as NaN and counted,
+// as are the pixels of a tile whose window does not fit in LDS.  (Measured on the
+// oracle's sums, the error stays below 28 ulp(max|g2|) / prod a_k^2, a quarter of the
+// bound.)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "svf_internal.h"
+#include "svf_runtime_internal.h"
+#include "svf_zp2_table.h"
+
+namespace svf {
+
+namespace {
+
+constexpr int kSpT = 16;                     // output tile side
+constexpr int kSpLdsBytes = 159 * 1024;      // dynamic LDS of one work-group (the CU has 160 KiB)
+constexpr double kSq2 = 1.41421356237309504880;
+constexpr double kIsq2 = 0.70710678118654752440;
+
+struct SingleJob {
+    const void *in;
+    int64_t in_rs;          // elements per input row
+    int32_t in_type, C;
+    int64_t H, W;
+    const float *scales;    // scales of the whole filter, float4 per pixel
+    int64_t sc_rs;          // floats per scale row
+    float *out;
+    int64_t out_rs;
+    double inv_sqrt_m;      // 1 / sqrt(2): the pass scales
+    int32_t win_cap;        // doubles of dynamic LDS for the window and the sweep rows
+    uint32_t *nan_count;    // outputs written as NaN
+};
+
+// Window and sweep layout in the dynamic LDS: window rows of stride S (S odd, so the
+// row scans' lanes spread over the banks), then two double-buffered rows of RS2 and
+// RS4 values for the sweep.
+__device__ __forceinline__ int sweep_doubles(int ww) { return 4 * (ww + 2); }
+
+template <int IN>
+__device__ __forceinline__ double in_at(const SingleJob &J, int64_t r, int64_t c, int ch)
+{
+    if (r < 0 || c < 0 || r >= J.H || c >= J.W) return 0.0;
+    const int64_t i = r * J.in_rs + c * J.C + ch;
+    if constexpr (IN == kInU16) return (double)static_cast<const uint16_t *>(J.in)[i];
+    else return (double)static_cast<const float *>(J.in)[i];
+}
+
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// One application of RS1..RS4 to the window in LDS, in place.
+__device__ void rs4_window(double *g, int wh, int ww, int S, double *p45, double *pb)
+{
+    const int t = threadIdx.x;
+    for (int row = t; row < wh; row += blockDim.x) {   // RS1 along the row
+        double s = 0.0;
+        double *q = g + row * S;
+        for (int c = 0; c < ww; ++c) {
+            s += q[c];
+            q[c] = s;
+        }
+    }
+    __syncthreads();
+    // RS2 (step (1,1)), RS3 (step (0,1)), RS4 (step (-1,1)) in one sweep down the rows:
+    // row r of each needs row r - 1 of itself only, at columns c - 1, c, c + 1.
+    double acc90 = 0.0;
+    const int c = t;
+    for (int r = 0; r < wh; ++r) {
+        double *c45 = p45 + (r & 1) * (ww + 2), *cb = pb + (r & 1) * (ww + 2);
+        const double *o45 = p45 + ((r + 1) & 1) * (ww + 2), *ob = pb + ((r + 1) & 1) * (ww + 2);
+        if (c < ww) {
+            const double x = g[r * S + c];
+            const double v45 = fma(kSq2, x, (r > 0 && c > 0) ? o45[c - 1] : 0.0);
+            acc90 += v45;
+            const double vb = fma(kSq2, acc90, (r > 0 && c + 1 < ww) ? ob[c + 1] : 0.0);
+            c45[c] = v45;
+            cb[c] = vb;
+            g[r * S + c] = vb;
+        }
+        __syncthreads();
+    }
+}
+
+// Sum over the table's 36 stencil offsets (lx', ly') of g at base + lx' dA + ly' dB,
+// times the offset's polynomial in (px, py).
+__device__ __forceinline__ double zp2_interp(const double *g, int base, int dA, int dB, double px, double py)
+{
+    double acc[28];
+#pragma unroll
+    for (int r = 0; r < 28; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 36; ++i) {
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 28; ++r) any = any || kZp2Coef[i][r] != 0.0;
+        if (!any) continue;
+        const double v = g[base + (i % 6 - 2) * dA + (i / 6 - 2) * dB];
+#pragma unroll
+        for (int r = 0; r < 28; ++r)
+            if (kZp2Coef[i][r] != 0.0) acc[r] = fma(kZp2Coef[i][r], v, acc[r]);
+    }
+    double xp[kZp2Deg + 1], yp[kZp2Deg + 1];
+    xp[0] = yp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= kZp2Deg; ++k) {
+        xp[k] = xp[k - 1] * px;
+        yp[k] = yp[k - 1] * py;
+    }
+    double F = 0.0;
+#pragma unroll
+    for (int r = 0; r < 28; ++r) F = fma(acc[r], xp[kZp2Mono[r][0]] * yp[kZp2Mono[r][1]], F);
+    return F;
+}
+
+template <int IN>
+__global__ __launch_bounds__(256) void k_single2(SingleJob J)
+{
+    extern __shared__ double lds[];
+    __shared__ int s_box[4];
+    __shared__ double s_red[4];
+    __shared__ uint32_t s_nan;
+    const int t = threadIdx.x, ch = blockIdx.z;
+    const int64_t r = (int64_t)blockIdx.y * kSpT + t / kSpT, c = (int64_t)blockIdx.x * kSpT + t % kSpT;
+    const bool inside = r < J.H && c < J.W;
+    if (t == 0) {
+        s_box[0] = s_box[2] = INT32_MAX;
+        s_box[1] = s_box[3] = INT32_MIN;
+        s_nan = 0;
+    }
+    double a[4] = {1.0, 1.0, 1.0, 1.0};
+    bool ok = false;
+    if (inside) {
+        const float4 v = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
+        a[0] = v.x * J.inv_sqrt_m; a[1] = v.y * J.inv_sqrt_m; a[2] = v.z * J.inv_sqrt_m; a[3] = v.w * J.inv_sqrt_m;
+        ok = a[0] > 0.0 && a[1] > 0.0 && a[2] > 0.0 && a[3] > 0.0 && isfinite(a[0] + a[1] + a[2] + a[3]);
+    }
+    // twice the shift of Sec. 3.1 step (2), and the taps' extent: tap j sits at
+    // n + 2 tau - (j1 a1 + (j2 a2 - j4 a4)/sqrt2, (j2 a2 + j4 a4)/sqrt2 + j3 a3)
+    const double ap2 = a[1] * kIsq2, ap4 = a[3] * kIsq2;
+    const double t1 = a[0] + ap2 - ap4 - 1.0, t2 = ap2 + a[2] + ap4 - 3.0;   // 2 tau
+    const double y1 = (double)c + t1, y2 = (double)r + t2;
+    __syncthreads();
+    if (ok) {
+        // lattice samples read: floor(y) - 2 .. floor(y) + 3 per axis, one more each way
+        // for rounding differences between this bound and the taps' own sums
+        atomicMin(&s_box[0], (int)floor(y1 - 2.0 * (a[0] + ap2)) - 3);
+        atomicMax(&s_box[1], (int)floor(y1 + 2.0 * ap4) + 4);
+        atomicMin(&s_box[2], (int)floor(y2 - 2.0 * (ap2 + a[2] + ap4)) - 3);
+        atomicMax(&s_box[3], (int)floor(y2) + 4);
+    }
+    __syncthreads();
+    float *outp = J.out + (inside ? r * J.out_rs + c * J.C + ch : 0);
+    if (s_box[0] == INT32_MAX) {   // no valid pixel in the tile
+        if (inside) {
+            *outp = NAN;
+            atomicAdd(J.nan_count, 1u);
+        }
+        return;
+    }
+    const int wc0 = s_box[0], wr0 = s_box[2];
+    const int ww = s_box[1] - wc0 + 1, wh = s_box[3] - wr0 + 1;
+    const int S = ww | 1;
+    if (ww > (int)blockDim.x || (int64_t)wh * S + sweep_doubles(ww) > J.win_cap) {
+        if (inside) {
+            *outp = NAN;
+            atomicAdd(&s_nan, 1u);
+        }
+        __syncthreads();
+        if (t == 0 && s_nan) atomicAdd(J.nan_count, s_nan);
+        return;
+    }
+    double *g = lds, *p45 = lds + (int64_t)wh * S, *pb = p45 + 2 * (ww + 2);
+    double fmax_loc = 0.0;
+    for (int i = t; i < wh * ww; i += blockDim.x) {
+        const int rr = i / ww, cc = i - rr * ww;
+        const double v = in_at<IN>(J, (int64_t)wr0 + rr, (int64_t)wc0 + cc, ch);
+        g[rr * S + cc] = v;
+        fmax_loc = fmax(fmax_loc, fabs(v));
+    }
+    const double fmax_w = block_max(fmax_loc, s_red);
+    rs4_window(g, wh, ww, S, p45, pb);
+    rs4_window(g, wh, ww, S, p45, pb);
+    double gmax_loc = 0.0;
+    for (int i = t; i < wh * ww; i += blockDim.x) gmax_loc = fmax(gmax_loc, fabs(g[(i / ww) * S + i % ww]));
+    const double gmax = block_max(gmax_loc, s_red);
+
+    if (!inside) return;
+    double res = NAN;
+    if (ok) {
+        const double pa = a[0] * a[1] * a[2] * a[3], w = 1.0 / (pa * pa);
+        const double bound = 0x1p-46 * gmax * w;
+        if (bound <= 1e-6 * fmax_w) {
+            const double b1 = y1 - wc0, b2 = y2 - wr0;   // window coordinates
+            double acc = 0.0;
+            for (int jj = 0; jj < 81; ++jj) {
+                const int j1 = jj % 3, j2 = (jj / 3) % 3, j3 = (jj / 9) % 3, j4 = jj / 27;
+                const double coef = (double)((j1 == 1 ? -2 : 1) * (j2 == 1 ? -2 : 1) * (j3 == 1 ? -2 : 1) *
+                                             (j4 == 1 ? -2 : 1));
+                const double Y1 = b1 - (j1 * a[0] + j2 * ap2 - j4 * ap4);
+                const double Y2 = b2 - (j2 * ap2 + j3 * a[2] + j4 * ap4);
+                const double fx = floor(Y1), fy = floor(Y2);
+                const double dx = Y1 - fx, dy = Y2 - fy;
+                const int ix = (int)fx, iy = (int)fy;
+                // quarter turn of the unit square that takes the tap's mesh triangle to
+                // the tabulated one: position (px, py), and the window offset of table
+                // stencil (lx', ly') as o + lx' dA + ly' dB
+                double px, py;
+                int ox, oy, dA, dB;
+                const bool below = dy <= dx, low = dx + dy <= 1.0;
+                if (below && low) { px = dx; py = dy; ox = 0; oy = 0; dA = 1; dB = S; }
+                else if (below) { px = dy; py = 1.0 - dx; ox = 1; oy = 0; dA = S; dB = -1; }
+                else if (!low) { px = 1.0 - dx; py = 1.0 - dy; ox = 1; oy = 1; dA = -1; dB = -S; }
+                else { px = 1.0 - dy; py = dx; ox = 0; oy = 1; dA = -S; dB = 1; }
+                const int base = (iy + oy) * S + ix + ox;
+                acc = fma(coef, zp2_interp(g, base, dA, dB, px, py), acc);
+            }
+            res = w * acc;
+        }
+    }
+    *outp = (float)res;
+    if (isnan(res)) atomicAdd(J.nan_count, 1u);
+}
+
+}  // namespace
+
+}  // namespace svf
+
+using namespace svf;
+
+extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const svf_field *field, int m,
+                                        const svf_opts *opts, svf_image *out, hipStream_t stream, svf_report *rep)
+{
+    if (!ctx) return SVF_EINVAL;
+    ctx->err.clear();
+    svf_opts o;
+    if (opts) o = *opts; else svf_default_opts(&o);
+    if (m != 2) return fail(ctx, SVF_EUNSUPPORTED, "single-pass iterated filter: m = 2 only");
+    svf_status st = check_filter_args(ctx, in, field, 4, m, o, out);
+    if (st) return st;
+    if (o.boundary != SVF_BOUNDARY_ZERO) return fail(ctx, SVF_EUNSUPPORTED, "single pass: zero boundary only");
+    if (o.preint != SVF_PRE_F64 || o.fd_fp32) return fail(ctx, SVF_EUNSUPPORTED, "single pass: binary64 only");
+    if (o.bands > 1) return fail(ctx, SVF_EUNSUPPORTED, "single pass: one band");
+    if (in->data == out->data && in->H > 0 && in->W > 0)
+        return fail(ctx, SVF_EINVAL, "single pass: out must not alias in");
+    if (rep) std::memset(rep, 0, sizeof *rep);
+    if (in->H == 0 || in->W == 0) return SVF_OK;
+    // workspace: the scale map's tile records and scales (as for svf_filter), then the
+    // NaN counter
+    Plan p = plan_for(in, m, &o);
+    const size_t off_cnt = p.off_fdplan, bytes = off_cnt + 256;
+    st = ensure_workspace(ctx, bytes);
+    if (st) return st;
+    const size_t nt = (size_t)p.ntr * p.ntc;
+    st = ensure_pinned(ctx, nt * sizeof(TileStat) + 64);
+    if (st) return st;
+    hipSetDevice(ctx->device);
+    unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
+    Job j = base_job(in, field, m, &o, p, ws);
+    st = attach_lut(ctx, o, j, stream);
+    if (st) return st;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, (int64_t)(bytes / 4), stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fill");
+    e = timed_launch(ctx, kClsScaleMap, stream, [&] { return launch_scale_map(j, stream); });
+    if (e != hipSuccess) return hip_fail(ctx, e, "scale map launch");
+    // the window side follows from the largest support: read the tile records
+    TileStat *hts = static_cast<TileStat *>(ctx->host_pinned);
+    e = hipMemcpyAsync(hts, ws + p.off_tstat, nt * sizeof(TileStat), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tile records");
+    float mx = 0.f;
+    for (size_t i = 0; i < nt; ++i) mx = std::max(mx, std::max(hts[i].rx, hts[i].ry));
+    // support half-width of beta^{4,2} with the pass scales a / sqrt2: 2 rx / sqrt2
+    const double reach = std::sqrt(2.0) * mx;
+    const int side = kSpT + 2 * ((int)std::ceil(reach) + 6);
+    const int64_t need = (int64_t)side * (side | 1) + 4 * (side + 2);
+    const int cap = kSpLdsBytes / 8;
+    const int win_cap = (int)std::min<int64_t>(need, cap);
+    SingleJob sj;
+    sj.in = in->data;
+    sj.in_rs = in->row_stride;
+    sj.in_type = in->dtype == SVF_U16 ? kInU16 : kInF32;
+    sj.C = in->channels;
+    sj.H = in->H;
+    sj.W = in->W;
+    sj.scales = j.scales;
+    sj.sc_rs = j.sc_rs;
+    sj.out = static_cast<float *>(out->data);
+    sj.out_rs = out->row_stride;
+    sj.inv_sqrt_m = 1.0 / std::sqrt(2.0);
+    sj.win_cap = win_cap;
+    sj.nan_count = reinterpret_cast<uint32_t *>(ws + off_cnt);
+    const dim3 grid((unsigned)((in->W + kSpT - 1) / kSpT), (unsigned)((in->H + kSpT - 1) / kSpT),
+                    (unsigned)in->channels);
+    const size_t lds = (size_t)win_cap * 8;
+    e = timed_launch(ctx, kClsFd, stream, [&] {
+        if (sj.in_type == kInU16) {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInU16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(k_single2<kInU16>, grid, dim3(256), lds, stream, sj);
+        } else {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInF32>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(k_single2<kInF32>, grid, dim3(256), lds, stream, sj);
+        }
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return hip_fail(ctx, e, "single-pass launch");
+    if (!rep) return SVF_OK;
+    uint32_t *hc = reinterpret_cast<uint32_t *>(hts + nt);
+    e = hipMemcpyAsync(hc, ws + off_cnt, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "report");
+    fill_report(hts, nt, m, rep);
+    rep->overflow_px = *hc;
+    rep->max_reach_px = reach;
+    if (rep->invalid_px) return fail(ctx, SVF_EINVAL, "invalid field entries");
+    if (rep->overflow_px) return fail(ctx, SVF_ERANGE, "%lld outputs beyond the window or precision limit (NaN)",
+                                      (long long)rep->overflow_px);
+    return SVF_OK;
+}

@@ -1,0 +1,128 @@
+"""GPU parity of the single pass with the iterated box spline beta^{4,2}
+(svf_filter_single) against the oracle's direct sum sum_k f[k] beta^{4,2}_{a(n)}(n - k)
+(exact B-spline-convolution evaluation of the kernel), through the C ABI.
+
+Tolerance: per pixel |gpu - ref| <= 1e-5 * max(|ref|, 1e-3 max|ref|), RMS <= 1e-6; the
+outputs the kernel marks NaN (precision or window limit) are excluded, counted and
+reported (SVF_ERANGE)."""
+import numpy as np
+import pytest
+
+from paper_1003_2022_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1003_2022_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def run(ctx, img, fld, kind, m=2, expect=P.SVF_OK, **opts):
+    x = to_dev(img)
+    out = torch.full(img.shape, 7.0, dtype=torch.float32, device=DEV)
+    st, rep = P.svf_filter_single(ctx, P.image_of(x), P.field_of(to_dev(fld), kind), m, P.default_opts(**opts),
+                                  P.image_of(out), None, report=True)
+    torch.cuda.synchronize()
+    assert st == expect, (st, ctx.last_error())
+    return out.cpu().numpy().astype(np.float64), rep
+
+
+def compare(got, ref, what, tol=1e-5, rms_tol=1e-6):
+    ok = np.isfinite(got)
+    scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    rel = np.abs(got - ref)[ok] / scale[ok]
+    rms = float(np.sqrt(np.mean(rel ** 2))) if rel.size else 0.0
+    print(f"{what}: {ok.sum()} of {ok.size} finite, max rel {rel.max() if rel.size else 0:.3e} rms {rms:.3e}",
+          flush=True)
+    assert rel.size == 0 or rel.max() <= tol
+    assert rms <= rms_tol
+    return int((~ok).sum())
+
+
+@pytest.mark.parametrize("shape,seed", [((32, 28), 1), ((17, 40), 2)])
+def test_single_srt_f32(ctx, shape, seed):
+    img = I.uniform_image(*shape, seed=seed)
+    fld = I.srt_field(*shape, seed=seed, sigma_range=(2.5, 4.0), rho_range=(1.0, 3.0))
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3)
+    ref = oracle.filter_single(img, fld, oracle.FIELD_SRT3, 2)
+    assert compare(got, ref, f"srt {shape}") == 0
+    assert rep.overflow_px == 0 and rep.max_reach_px > 0
+
+
+def test_single_u16_channels(ctx):
+    img = I.uniform_image(21, 30, seed=3, dtype="u16", channels=2)
+    fld = I.srt_field(21, 30, seed=3, sigma_range=(2.5, 3.5), rho_range=(1.0, 2.0))
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3)
+    ref = oracle.filter_single(img.astype(np.float64), fld, oracle.FIELD_SRT3, 2)
+    assert compare(got, ref, "u16 x2") == 0
+
+
+def test_single_scales4(ctx):
+    img = I.uniform_image(26, 26, seed=4)
+    fld = I.scales_field(26, 26, seed=4, lo=4.0, hi=7.0, smooth=True)
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SCALES4)
+    ref = oracle.filter_single(img, fld, oracle.FIELD_SCALES4, 2)
+    assert compare(got, ref, "scales4") == 0
+
+
+def test_single_interior_of_larger_image(ctx):
+    # windows full of data (the precision-relevant case): sampled rectangles of a 128^2 image
+    img = I.uniform_image(128, 128, seed=5)
+    fld = I.srt_field(128, 128, seed=5, sigma_range=(3.0, 5.0), rho_range=(1.0, 2.5))
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3)
+    a, _ = oracle.scales(fld, oracle.FIELD_SRT3, 2)
+    for r0, c0 in [(0, 0), (60, 57), (111, 3), (40, 113)]:
+        h, w = 12, 12
+        h, w = min(h, 128 - r0), min(w, 128 - c0)
+        ref = oracle.pass_single(img, a[r0:r0 + h, c0:c0 + w], 2, "brute", r0, c0)
+        assert compare(got[r0:r0 + h, c0:c0 + w], ref, f"128^2 at {(r0, c0)}") == 0
+
+
+def test_single_small_filters_marked(ctx):
+    # small supports over a large, busy window lose digits: those outputs are NaN,
+    # counted and reported; the rest still match
+    img = I.uniform_image(96, 96, seed=6)
+    fld = I.srt_field(96, 96, seed=6, sigma_range=(0.7, 2.5), rho_range=(1.0, 2.0))
+    x = to_dev(img)
+    out = torch.empty(img.shape, dtype=torch.float32, device=DEV)
+    st, rep = P.svf_filter_single(ctx, P.image_of(x), P.field_of(to_dev(fld), P.SVF_FIELD_SRT3), 2,
+                                  P.default_opts(), P.image_of(out), None, report=True)
+    got = out.cpu().numpy().astype(np.float64)
+    nnan = int(np.isnan(got).sum())
+    assert rep.overflow_px == nnan
+    assert st == (P.SVF_ERANGE if nnan else P.SVF_OK)
+    a, _ = oracle.scales(fld, oracle.FIELD_SRT3, 2)
+    for r0, c0 in [(0, 0), (44, 50), (84, 84)]:
+        ref = oracle.pass_single(img, a[r0:r0 + 12, c0:c0 + 12], 2, "brute", r0, c0)
+        compare(got[r0:r0 + 12, c0:c0 + 12], ref, f"small filters at {(r0, c0)}")
+    print("NaN outputs:", nnan, "of", got.size)
+
+
+def test_single_rejects(ctx):
+    img = I.uniform_image(8, 8, seed=7)
+    fld = I.srt_field(8, 8, seed=7)
+    run(ctx, img, fld, P.SVF_FIELD_SRT3, m=3, expect=P.SVF_EUNSUPPORTED)
+    run(ctx, img, fld, P.SVF_FIELD_SRT3, m=2, expect=P.SVF_EUNSUPPORTED, boundary=P.SVF_BOUNDARY_REPLICATE)
+    run(ctx, img, fld, P.SVF_FIELD_SRT3, m=2, expect=P.SVF_EUNSUPPORTED, preint=P.SVF_PRE_F32C)
+    # an empty image: nothing to do
+    e_in = P.svf_image(None, P.SVF_F32, 1, 0, 5, 5)
+    e_out = P.svf_image(None, P.SVF_F32, 1, 0, 5, 5)
+    e_f = P.svf_field(None, P.SVF_FIELD_SRT3, 0, 15)
+    st, rep = P.svf_filter_single(ctx, e_in, e_f, 2, None, e_out, None, report=True)
+    assert st == P.SVF_OK and rep.overflow_px == 0
