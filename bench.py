@@ -38,10 +38,14 @@ Beside it, in the same JSON line:
                 FP32 images: time per filter (and, at 512^2, the latency of one
                 synchronous call), beside the paper's ~100 ms per 512^2 filter
                 (Java, 2.66 GHz CPU);
-  cpu_baseline  the CPU FP64 oracle timed on a bounded sample.
+  single_pass   one pass with the iterated box spline beta^(4,2) (svf_filter_single) on
+                a 2048 x 2048 FP32 image with sigma 3-12 px: time, kernel split, NaN
+                outputs, FP64 roofline of its kernel;
+  cpu_baseline  the CPU FP64 oracle timed on a bounded sample (and on a sample of the
+                single-pass workload, by its direct sum, with the GPU output compared).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve] [--no-precision]
-                    [--no-smooth] [--no-lut] [--no-table2]
+                    [--no-smooth] [--no-lut] [--no-table2] [--no-single]
                     [--calib-copy] [--preint f64|f32c] [--tile T] [--loads F,...] [--serve-requests N]
 """
 from __future__ import annotations
@@ -67,7 +71,8 @@ FP64_VECTOR_PEAK = 78.6        # TFLOP/s
 H = W = 4096
 ORDER = 2
 SEED = 3000
-# algorithmic work per output pixel and pass (derivations in the design doc)
+# algorithmic work per output pixel and pass: the difference's FP64 operations, and the bytes of
+# one read of f and of the field, the window sums written and read once, the output written
 FD_FLOPS_PER_PX = 640          # FP64 flops (FMA = 2) of the 16-tap difference with 7-point ZP interpolation
 ALGO_BYTES_PER_PX_PASS = 36    # f 4 + field 12 + g write 8 + g read 8 + out 4
 # sources of the finite-difference kernel: its file and the device helpers it includes
@@ -111,7 +116,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(img, fld, kind, f32_out, img16=None, u16_out=None):
+def cpu_baseline(img, fld, kind, f32_out, img16=None, u16_out=None, single=None):
     """Time the CPU oracle (binary64 fast algorithm, OpenMP) on a bounded sample of the workload, with
     every core the process may run on and with one thread, and compare the GPU outputs of every
     pre-integration variant with it element by element on the sample.
@@ -147,6 +152,23 @@ def cpu_baseline(img, fld, kind, f32_out, img16=None, u16_out=None):
     oracle.filter_region(img, fld, kind, ORDER, CPU_RECT_1T)
     dt1 = time.perf_counter() - t
     oracle.set_threads(cores)
+    single_res = None
+    if single is not None:
+        # the single-pass leg's sample: the oracle's direct sum with beta^{4,2}
+        s_img, s_fld, s_out = single
+        sr0, sc0, sh, sw = SP_RECT
+        a, _ = oracle.scales(s_fld[sr0:sr0 + sh, sc0:sc0 + sw], kind, 2)
+        t = time.perf_counter()
+        s_ref = oracle.pass_single(s_img, a, 2, "brute", sr0, sc0)
+        dts = time.perf_counter() - t
+        ok = np.isfinite(s_out)
+        mx, rms = rel_errors(np.where(ok, s_out, s_ref), s_ref)
+        log(f"single pass vs oracle direct sum: max rel {mx:.2e} rms {rms:.2e} ({int((~ok).sum())} NaN)")
+        single_res = {"value": round(sh * sw / dts / 1e6, 6), "unit": "Mpixel/s", "cores": used,
+                      "sample": f"{sh}x{sw} output pixels at ({sr0},{sc0}) of the single-pass workload, direct sum "
+                                f"sum_k f[k] beta^(4,2)(n - k), {dts:.1f} s",
+                      "parity": {"max_rel": mx, "rms_rel": rms, "nan_outputs": int((~ok).sum()),
+                                 "within_1e-5_1e-6": bool(mx <= 1e-5 and rms <= 1e-6)}}
     return {
         "value": round(h * w / dt / 1e6, 4),
         "unit": "Mpixel/s",
@@ -161,6 +183,7 @@ def cpu_baseline(img, fld, kind, f32_out, img16=None, u16_out=None):
         "parity_vs_oracle": {"region": list(CPU_RECT), "tolerance": "max rel 1e-5, RMS rel 1e-6 per pixel "
                              "(relative to max(|ref|, 1e-3 max|ref|)); the FP32 difference is reported only",
                              "variants": parity},
+        "single_pass": single_res,
     }
 
 
@@ -451,6 +474,76 @@ def smoothing_leg(P, I, ctx, torch, steps=5):
     }
 
 
+# ----------------------------------------------------------------------------- single-pass beta^{4,2} leg
+
+SP_N = 2048
+SP_SIGMA = (3.0, 12.0)
+SP_RECT = (1000, 1000, 48, 48)    # the oracle's sample of the single-pass workload (rows, cols, h, w)
+
+
+def zp2_nonzeros():
+    """Non-zero coefficients of the ZP*ZP table (the FMAs of one tap's interpolation)."""
+    text = (ROOT / "paper_1003_2022_amd" / "csrc" / "svf_zp2_table.h").read_text()
+    body = text.split("kZp2Coef[36][28] = {", 1)[1]
+    vals = re.findall(r"[-+]?\d[\d.eE+-]*", re.sub(r"//[^\n]*", "", body.split("};", 1)[0]))
+    return sum(1 for v in vals if float(v) != 0.0)
+
+
+def single_leg(P, I, ctx, torch, steps=5):
+    """svf_filter_single (one pass with beta^{4,2}) on a 2048^2 FP32 image with a smooth
+    (sigma 3-12 px, rho 1-3) field: time, kernel split, NaN outputs, FP64 roofline."""
+    dev = torch.device("cuda:0")
+    img = I.uniform_image(SP_N, SP_N, SEED + 5)
+    fld = I.srt_field(SP_N, SP_N, SEED + 5, sigma_range=SP_SIGMA, rho_range=(1.0, 3.0))
+    ti, tf = torch.from_numpy(img).to(dev), torch.from_numpy(fld).to(dev)
+    out = torch.empty_like(ti)
+    im_d, f_d, out_d = P.image_of(ti), P.field_of(tf, P.SVF_FIELD_SRT3), P.image_of(out)
+    o = P.default_opts()
+    stream = torch.cuda.current_stream()
+    st, rep = P.svf_filter_single(ctx, im_d, f_d, 2, o, out_d, stream, report=True)
+    P.svf_filter_single(ctx, im_d, f_d, 2, o, out_d, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        P.svf_filter_single(ctx, im_d, f_d, 2, o, out_d, stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    P.svf_set_timing(ctx, True)
+    for k in ("scale_map", "fd"):
+        P.svf_kernel_time(ctx, k, reset=True)
+    for _ in range(steps):
+        P.svf_filter_single(ctx, im_d, f_d, 2, o, out_d, stream)
+    torch.cuda.synchronize()
+    kt = {k: P.svf_kernel_time(ctx, k) for k in ("scale_map", "fd")}
+    P.svf_set_timing(ctx, False)
+    us = {k: tot / max(n, 1) * 1e3 for k, (tot, n) in kt.items()}
+    # FP64 work per pixel: per tap the table contraction (2 flops per non-zero coefficient),
+    # the degree-6 evaluation (28 FMAs, 12 powers, 28 monomial products) and the tap position
+    # (about 10); 81 taps
+    per_tap = 2 * zp2_nonzeros() + 2 * 28 + 12 + 28 + 10
+    flops_px = 81 * per_tap
+    achieved = flops_px * SP_N * SP_N / (us["fd"] * 1e-6) / 1e12
+    r0, c0, h, w = SP_RECT
+    log(f"single pass beta^(4,2): {ms:.3f} ms/filter, {SP_N * SP_N / (ms * 1e-3) / 1e6:.1f} Mpixel/s; kernel "
+        f"{us['fd']:.1f} us = {achieved:.1f} TFLOP/s FP64; NaN outputs {rep.overflow_px}")
+    res = {
+        "workload": f"{SP_N}x{SP_N} f32 uniform[0,1) image (seed {SEED + 5}), per-pixel (sigma {SP_SIGMA[0]:g}-"
+                    f"{SP_SIGMA[1]:g} px, rho 1-3, theta 0-pi) smooth field; one pass with beta^(4,2) "
+                    "(scales a/sqrt2), zero boundary, FP64",
+        "status": int(st),
+        "ms_per_filter": round(ms, 3),
+        "Mpixel_s": round(SP_N * SP_N / (ms * 1e-3) / 1e6, 1),
+        "kernel_avg_us": {k: round(v, 2) for k, v in us.items()},
+        "nan_outputs": int(rep.overflow_px),
+        "max_reach_px": round(rep.max_reach_px, 2),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_VECTOR_PEAK, 4), "traffic": None,
+                     "kernel": "k_single2 (window sums in LDS, 81 taps with ZP*ZP interpolation)",
+                     "algorithmic_flops_per_px": flops_px},
+    }
+    return res, (img, fld, out.cpu().numpy()[r0:r0 + h, c0:c0 + w].copy())
+
+
 # ----------------------------------------------------------------------------- precision and scale-table legs
 
 def rel_errors(got, ref):
@@ -576,6 +669,7 @@ def main():
     ap.add_argument("--no-smooth", action="store_true", help="skip the feature-preserving smoothing leg")
     ap.add_argument("--no-lut", action="store_true", help="skip the look-up-table scale-map leg")
     ap.add_argument("--no-table2", action="store_true", help="skip the Table 2 (constant-size sweep) leg")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-pass beta^(4,2) leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--preint", default="f64", choices=["f64", "f32c"])
@@ -727,6 +821,9 @@ def main():
         line["scale_lut"] = lut_leg(P, ctx, ti, tf, fld, torch)
     if not args.no_smooth:
         line["smoothing"] = smoothing_leg(P, I, ctx, torch)
+    single = None
+    if not args.no_single:
+        line["single_pass"], single = single_leg(P, I, ctx, torch)
     if not args.no_batch:
         line["batch"] = batch_leg(P, I, ctx, ti, torch)
     if not args.no_serve:
@@ -734,7 +831,7 @@ def main():
                                       args.serve_requests, args.serve_step_mpx)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
-        line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3, f32_crops, img16, u16_crops)
+        line["cpu_baseline"] = cpu_baseline(img, fld, P.SVF_FIELD_SRT3, f32_crops, img16, u16_crops, single)
     ctx.close()
     print(json.dumps(line), flush=True)
 
