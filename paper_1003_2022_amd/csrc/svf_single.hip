@@ -16,7 +16,9 @@
 // One work-group per 16 x 16 output tile and channel: the tile's window (every lattice
 // sample its 256 pixels' taps read) is loaded into LDS as binary64, summed twice in
 // place (RS1 along the rows, then RS2, RS3, RS4 in one top-to-bottom sweep of the rows
-// with one barrier per row), and each thread evaluates its pixel's 81 taps from LDS.
+// with one barrier per row), and two threads per pixel evaluate its 81 taps from LDS
+// (41 and 40), whose partial sums meet in LDS.  A large window takes the CU's whole LDS,
+// so the second thread per pixel is what gives each SIMD two waves.
 //
 // Precision: the doubled sums grow like the window side^8, and the difference cancels
 // all but ~prod a_k^2 of that.  A pixel whose rounding bound 2^-46 max|g2| / prod a_k^2
@@ -40,7 +42,7 @@ namespace svf {
 namespace {
 
 constexpr int kSpT = 16;                     // output tile side
-constexpr int kSpLdsBytes = 159 * 1024;      // dynamic LDS of one work-group (the CU has 160 KiB)
+constexpr int kSpLdsBytes = 157 * 1024;      // dynamic LDS of one work-group (160 KiB per CU, less the static part)
 constexpr double kSq2 = 1.41421356237309504880;
 constexpr double kIsq2 = 0.70710678118654752440;
 
@@ -72,6 +74,8 @@ __device__ __forceinline__ double in_at(const SingleJob &J, int64_t r, int64_t c
     else return (double)static_cast<const float *>(J.in)[i];
 }
 
+constexpr int kSpThreads = 512;              // two threads per output pixel, each half of its taps
+
 __device__ __forceinline__ double block_max(double v, double *red)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -79,7 +83,9 @@ __device__ __forceinline__ double block_max(double v, double *red)
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[wave] = v;
     __syncthreads();
-    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double m = red[0];
+    for (int k = 1; k < kSpThreads / 64; ++k) m = fmax(m, red[k]);
+    return m;
 }
 
 // One application of RS1..RS4 to the window in LDS, in place.
@@ -147,14 +153,17 @@ __device__ __forceinline__ double zp2_interp(const double *g, int base, int dA, 
 }
 
 template <int IN>
-__global__ __launch_bounds__(256) void k_single2(SingleJob J)
+__global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
 {
     extern __shared__ double lds[];
     __shared__ int s_box[4];
-    __shared__ double s_red[4];
+    __shared__ double s_red[kSpThreads / 64];
+    __shared__ double s_part[kSpT * kSpT];
     __shared__ uint32_t s_nan;
-    const int t = threadIdx.x, ch = blockIdx.z;
-    const int64_t r = (int64_t)blockIdx.y * kSpT + t / kSpT, c = (int64_t)blockIdx.x * kSpT + t % kSpT;
+    // thread t: pixel t % 256 of the tile; the first half of the threads takes taps 0..40,
+    // the second half taps 41..80 (two waves per SIMD with one work-group per CU)
+    const int t = threadIdx.x, ch = blockIdx.z, px_i = t & (kSpT * kSpT - 1), half = t / (kSpT * kSpT);
+    const int64_t r = (int64_t)blockIdx.y * kSpT + px_i / kSpT, c = (int64_t)blockIdx.x * kSpT + px_i % kSpT;
     const bool inside = r < J.H && c < J.W;
     if (t == 0) {
         s_box[0] = s_box[2] = INT32_MAX;
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(256) void k_single2(SingleJob J)
     __syncthreads();
     float *outp = J.out + (inside ? r * J.out_rs + c * J.C + ch : 0);
     if (s_box[0] == INT32_MAX) {   // no valid pixel in the tile
-        if (inside) {
+        if (inside && half == 0) {
             *outp = NAN;
             atomicAdd(J.nan_count, 1u);
         }
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(256) void k_single2(SingleJob J)
     const int ww = s_box[1] - wc0 + 1, wh = s_box[3] - wr0 + 1;
     const int S = ww | 1;
     if (ww > (int)blockDim.x || (int64_t)wh * S + sweep_doubles(ww) > J.win_cap) {
-        if (inside) {
+        if (inside && half == 0) {
             *outp = NAN;
             atomicAdd(&s_nan, 1u);
         }
@@ -218,15 +227,14 @@ __global__ __launch_bounds__(256) void k_single2(SingleJob J)
     for (int i = t; i < wh * ww; i += blockDim.x) gmax_loc = fmax(gmax_loc, fabs(g[(i / ww) * S + i % ww]));
     const double gmax = block_max(gmax_loc, s_red);
 
-    if (!inside) return;
-    double res = NAN;
-    if (ok) {
-        const double pa = a[0] * a[1] * a[2] * a[3], w = 1.0 / (pa * pa);
-        const double bound = 0x1p-46 * gmax * w;
-        if (bound <= 1e-6 * fmax_w) {
+    const double pa = a[0] * a[1] * a[2] * a[3], w = 1.0 / (pa * pa);
+    const bool run = inside && ok && 0x1p-46 * gmax * w <= 1e-6 * fmax_w;
+    double acc = 0.0;
+    if (run) {
+        {
             const double b1 = y1 - wc0, b2 = y2 - wr0;   // window coordinates
-            double acc = 0.0;
-            for (int jj = 0; jj < 81; ++jj) {
+            const int j_end = half ? 81 : 41;
+            for (int jj = half ? 41 : 0; jj < j_end; ++jj) {
                 const int j1 = jj % 3, j2 = (jj / 3) % 3, j3 = (jj / 9) % 3, j4 = jj / 27;
                 const double coef = (double)((j1 == 1 ? -2 : 1) * (j2 == 1 ? -2 : 1) * (j3 == 1 ? -2 : 1) *
                                              (j4 == 1 ? -2 : 1));
@@ -248,11 +256,14 @@ __global__ __launch_bounds__(256) void k_single2(SingleJob J)
                 const int base = (iy + oy) * S + ix + ox;
                 acc = fma(coef, zp2_interp(g, base, dA, dB, px, py), acc);
             }
-            res = w * acc;
         }
     }
+    if (half) s_part[px_i] = acc;
+    __syncthreads();
+    if (!inside || half) return;
+    const double res = run ? w * (acc + s_part[px_i]) : NAN;
     *outp = (float)res;
-    if (isnan(res)) atomicAdd(J.nan_count, 1u);
+    if (!run) atomicAdd(J.nan_count, 1u);
 }
 
 }  // namespace
@@ -330,11 +341,11 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
         if (sj.in_type == kInU16) {
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInU16>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(k_single2<kInU16>, grid, dim3(256), lds, stream, sj);
+            hipLaunchKernelGGL(k_single2<kInU16>, grid, dim3(kSpThreads), lds, stream, sj);
         } else {
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInF32>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(k_single2<kInF32>, grid, dim3(256), lds, stream, sj);
+            hipLaunchKernelGGL(k_single2<kInF32>, grid, dim3(kSpThreads), lds, stream, sj);
         }
         return hipGetLastError();
     });
