@@ -255,8 +255,8 @@ svf_status svf_filter_noalloc(svf_ctx *ctx, const svf_image *in, const svf_field
  * descriptor table (a work-group finds its image by a search over prefix
  * counts).  With use_graph != 0 the launch sequence is captured once per
  * distinct shape set into a HIP graph and replayed.  Results equal n
- * svf_filter calls with the same options (opts.tile 0 means 256 here) up to
- * rounding.  Returns after enqueueing (the descriptor upload is
+ * svf_filter calls with the same options bit for bit (opts.tile 0 means 256
+ * here, so it is svf_filter with opts.tile = 256 that the batch reproduces).  Returns after enqueueing (the descriptor upload is
  * stream-ordered).
  */
 svf_status svf_filter_batch(svf_ctx *ctx, int n, const svf_image *in, const svf_field *fields, const int *orders,
@@ -331,7 +331,7 @@ svf_status svf_smooth_adaptive(svf_ctx *ctx, const svf_image *in, const svf_st_p
  * request's first pass) of the requests in flight, oldest first, up to a
  * per-step work budget, all through the batched persistent kernels.  Requests
  * join and leave between steps.  Each request computes what
- * svf_filter_batch computes for it (svf_filter's result up to rounding;
+ * svf_filter_batch computes for it (svf_filter's result bit for bit;
  * opts.tile 0 means 256 here), bit for bit whatever the mix it ran in.  Input, field and output stay in caller-owned device memory
  * that must remain valid until the request is done.  The integer
  * pre-integration is not offered by the server (opts.preint must be F64 or

@@ -1,12 +1,12 @@
 """GPU tests of the batched launch path and of the serving loop.
 
 * svf_filter_batch (eager and HIP-graph replays) equals per-image svf_filter
-  with the same options to 1e-6 (the batched pre-integration sums in another
-  order; the outputs are float32), every replay equals the first bit for bit,
+  with the same options (the same tile, so the same windows and the same
+  kernels' arithmetic) bit for bit, every replay equals the first bit for bit,
   and the oracle to 1e-5;
 * the server: every request's output is bitwise identical whether it is served
-  alone or in a mix, equals svf_filter with the same options to 1e-6, and
-  equals the CPU FP64 oracle to 1e-5 (relative, per pixel);
+  alone or in a mix, and to svf_filter with the same options, and equals the CPU
+  FP64 oracle to 1e-5 (relative, per pixel);
 * admission: a request larger than the memory budget is rejected at submit;
 * failure handling forced from the host: cancellation of queued and in-flight
   requests, a full queue, a context workspace budget.
@@ -102,8 +102,9 @@ def test_batch_matches_single_and_oracle(ctx, cases, use_graph):
             ref = single(ctx, c[3], c[4], c[2], tile=256)
             got = outs[i].cpu().numpy()
             e = rel_err(got, ref)
-            print(f"graph={use_graph} rep {rep} case {i}: vs single {e:.2e}", flush=True)
-            assert e <= 1e-6
+            print(f"graph={use_graph} rep {rep} case {i}: vs single {e:.2e} bitwise {np.array_equal(got, ref)}",
+                  flush=True)
+            assert np.array_equal(got, ref), f"case {i}: batch differs from svf_filter (max rel {e:.2e})"
             if rep == 0:
                 first.append(got)
             else:
@@ -172,7 +173,9 @@ def test_server_mix_equals_alone(ctx, cases):
         assert res[i].t_done_us >= res[i].t_admit_us >= res[i].t_submit_us
     for i, c in enumerate(cases):
         ref = single(ctx, c[3], c[4], c[2], tile=256)
-        assert rel_err(alone[i], ref) <= 1e-6
+        print(f"server case {i}: vs single {rel_err(alone[i], ref):.2e} bitwise {np.array_equal(alone[i], ref)}",
+              flush=True)
+        assert np.array_equal(alone[i], ref), f"request {i}: server differs from svf_filter"
     img, fld, order = cases[2][:3]
     assert rel_err(alone[2], oracle.filter(img, fld, oracle.FIELD_SRT3, order)) <= 1e-5
 
