@@ -489,10 +489,10 @@ SP_RECT = (1000, 1000, 48, 48)    # the oracle's sample of the single-pass workl
 
 
 def zp2_nonzeros():
-    """Non-zero coefficients of the ZP*ZP table (the FMAs of one tap's interpolation)."""
+    """Non-zero coefficients of the ZP*ZP table (the FMAs of one tap's contraction)."""
     text = (ROOT / "paper_1003_2022_amd" / "csrc" / "svf_zp2_table.h").read_text()
-    body = text.split("kZp2Coef[36][28] = {", 1)[1]
-    vals = re.findall(r"[-+]?\d[\d.eE+-]*", re.sub(r"//[^\n]*", "", body.split("};", 1)[0]))
+    body = text.split("kZp2Half[18][28] = {", 1)[1].split("};", 1)[0]
+    vals = re.findall(r"[-+]?\d[\d.eE+-]*", re.sub(r"//[^\n]*", "", body))
     return sum(1 for v in vals if float(v) != 0.0)
 
 
@@ -524,10 +524,10 @@ def single_leg(P, I, ctx, torch, steps=5):
     kt = {k: P.svf_kernel_time(ctx, k) for k in ("scale_map", "fd")}
     P.svf_set_timing(ctx, False)
     us = {k: tot / max(n, 1) * 1e3 for k, (tot, n) in kt.items()}
-    # FP64 work per pixel: per tap the table contraction (2 flops per non-zero coefficient),
-    # the degree-6 evaluation (28 FMAs, 12 powers, 28 monomial products) and the tap position
-    # (about 10); 81 taps
-    per_tap = 2 * zp2_nonzeros() + 2 * 28 + 12 + 28 + 10
+    # FP64 work per pixel: per tap the table contraction (2 flops per non-zero coefficient,
+    # and a sum and a difference per mirror pair of samples), the degree-6 evaluation
+    # (28 FMAs, 12 powers, 28 monomial products) and the tap position (about 10); 81 taps
+    per_tap = 2 * zp2_nonzeros() + 2 * 18 + 2 * 28 + 12 + 28 + 10
     flops_px = 81 * per_tap
     achieved = flops_px * SP_N * SP_N / (us["fd"] * 1e-6) / 1e12
     r0, c0, h, w = SP_RECT

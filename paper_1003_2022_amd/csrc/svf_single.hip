@@ -121,29 +121,37 @@ __device__ void rs4_window(double *g, int wh, int ww, int S, double *p45, double
     }
 }
 
-// Sum over the table's 36 stencil offsets (lx', ly') of g at base + lx' dA + ly' dB,
-// times the offset's polynomial in (px, py).
+// F2 at a point of the tabulated triangle: the sum over the 36 stencil offsets of g
+// times the offset's polynomial.  Offsets pair up as (lx', ly') and (1 - lx', ly')
+// (mirror images about dx = 1/2, where T0 is symmetric): with u = px - 1/2 the pair
+// contributes c[p,q] u^p py^q (g + g') for even p and (g - g') for odd p.  The table
+// stencil (lx', ly') sits at window offset base + lx' dA + ly' dB.  The coefficients
+// are integers (the exact ones times kZp2Den): immediate operands of the FMAs, and the
+// result is kZp2Den times F2.
 __device__ __forceinline__ double zp2_interp(const double *g, int base, int dA, int dB, double px, double py)
 {
     double acc[28];
 #pragma unroll
     for (int r = 0; r < 28; ++r) acc[r] = 0.0;
 #pragma unroll
-    for (int i = 0; i < 36; ++i) {
+    for (int i = 0; i < 18; ++i) {
         bool any = false;
 #pragma unroll
-        for (int r = 0; r < 28; ++r) any = any || kZp2Coef[i][r] != 0.0;
+        for (int r = 0; r < 28; ++r) any = any || kZp2Half[i][r] != 0.0;
         if (!any) continue;
-        const double v = g[base + (i % 6 - 2) * dA + (i / 6 - 2) * dB];
+        const int lx = i % 3 - 2, ly = i / 3 - 2;
+        const double v0 = g[base + lx * dA + ly * dB], v1 = g[base + (1 - lx) * dA + ly * dB];
+        const double sum = v0 + v1, dif = v0 - v1;
 #pragma unroll
         for (int r = 0; r < 28; ++r)
-            if (kZp2Coef[i][r] != 0.0) acc[r] = fma(kZp2Coef[i][r], v, acc[r]);
+            if (kZp2Half[i][r] != 0.0) acc[r] = fma(kZp2Half[i][r], (kZp2Mono[r][0] & 1) ? dif : sum, acc[r]);
     }
+    const double u = px - 0.5;
     double xp[kZp2Deg + 1], yp[kZp2Deg + 1];
     xp[0] = yp[0] = 1.0;
 #pragma unroll
     for (int k = 1; k <= kZp2Deg; ++k) {
-        xp[k] = xp[k - 1] * px;
+        xp[k] = xp[k - 1] * u;
         yp[k] = yp[k - 1] * py;
     }
     double F = 0.0;
@@ -227,8 +235,8 @@ __global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
     for (int i = t; i < wh * ww; i += blockDim.x) gmax_loc = fmax(gmax_loc, fabs(g[(i / ww) * S + i % ww]));
     const double gmax = block_max(gmax_loc, s_red);
 
-    const double pa = a[0] * a[1] * a[2] * a[3], w = 1.0 / (pa * pa);
-    const bool run = inside && ok && 0x1p-46 * gmax * w <= 1e-6 * fmax_w;
+    const double pa = a[0] * a[1] * a[2] * a[3], w = 1.0 / (pa * pa * kZp2Den);   // table scale folded in
+    const bool run = inside && ok && 0x1p-46 * gmax * (w * kZp2Den) <= 1e-6 * fmax_w;
     double acc = 0.0;
     if (run) {
         {

@@ -18,15 +18,23 @@ values on the order-8 principal lattice of T0 (45 points, exact least squares;
 the residual is checked to be zero).  The other three triangles of the unit square
 map onto T0 by the square's quarter turns, under which M_c is invariant.
 
-Writes csrc/svf_zp2_table.h: kZp2Coef[36][28] (binary64, rounded from the exact
-rationals), stencil offset (lx, ly) = (i % 6 - 2, i / 6 - 2), monomial dx^p dy^q in
-the order p + q = 0, 1, ..., 6 and, within a degree, q = 0, 1, ....
+T0 is symmetric about dx = 1/2 and M_c under x -> -x, so with u = dx - 1/2 the
+offsets l = (lx, ly) and l' = (1 - lx, ly) have W_l'(u, dy) = W_l(-u, dy) (checked
+exactly): for the pair, g_l W_l + g_l' W_l' = sum over the monomials u^p dy^q of
+c_l[p, q] u^p dy^q times (g_l + g_l') for even p and (g_l - g_l') for odd p.  The
+table keeps the 18 offsets with lx <= 0.
 
-Usage: python -m paper_1003_2022_amd.gen_zp2_table   (takes about a minute)
+Writes csrc/svf_zp2_table.h: kZp2Half[18][28], the exact rational coefficients times
+their common denominator kZp2Den (integers below 2^21), pair i = offsets
+(i % 3 - 2, i / 3 - 2) and (3 - i % 3, i / 3 - 2), monomial u^p dy^q in the order
+p + q = 0, 1, ..., 6 and, within a degree, q = 0, 1, ....
+
+Usage: python -m paper_1003_2022_amd.gen_zp2_table   (a few seconds)
 """
 from __future__ import annotations
 
 from fractions import Fraction as Fr
+from math import comb, lcm
 from pathlib import Path
 
 DIRS = [(1, 0), (1, 1), (0, 1), (-1, 1)] * 2
@@ -139,21 +147,50 @@ def main(out: Path | None = None) -> str:
     # partition of unity, as a polynomial identity
     for r in range(len(MONO)):
         assert sum(t[r] for t in table) == (1 if r == 0 else 0)
+    # in u = dx - 1/2: expand (u + 1/2)^p
+    def shift(coef):
+        out = {m: Fr(0) for m in MONO}
+        for c, (p, q) in zip(coef, MONO):
+            if c == 0:
+                continue
+            for k in range(p + 1):   # (u + 1/2)^p = sum_k C(p, k) u^k (1/2)^(p - k)
+                out[(k, q)] += c * Fr(comb(p, k)) * Fr(1, 2 ** (p - k))
+        return [out[m] for m in MONO]
+    cu = [shift(t) for t in table]
+    half = []
+    for i in range(18):
+        lx, ly = i % 3 - 2, i // 3 - 2
+        a = cu[(ly + 2) * 6 + (lx + 2)]
+        b = cu[(ly + 2) * 6 + (1 - lx + 2)]
+        for (p, q), ca, cb in zip(MONO, a, b):
+            assert cb == (ca if p % 2 == 0 else -ca), f"mirror pair {(lx, ly)}"
+        half.append(a)
+    # one common denominator makes every coefficient a small integer: exact in binary64
+    # and, with at most 21 significant bits, an immediate operand of the FMAs
+    den = 1
+    for row in half:
+        for c in row:
+            den = lcm(den, c.denominator)
     rows = []
-    for i, coef in enumerate(table):
-        lx, ly = i % 6 - 2, i // 6 - 2
-        body = ", ".join(repr(float(c)) for c in coef)
-        rows.append(f"    {{{body}}},   // ({lx}, {ly})")
+    for i, coef in enumerate(half):
+        lx, ly = i % 3 - 2, i // 3 - 2
+        ints = [c * den for c in coef]
+        assert all(v.denominator == 1 and abs(v) < 2 ** 21 for v in ints)
+        body = ", ".join(f"{int(v)}.0" for v in ints)
+        rows.append(f"    {body},   // ({lx}, {ly}) and ({1 - lx}, {ly})")
     text = (
         "// svf_zp2_table.h -- generated by paper_1003_2022_amd/gen_zp2_table.py; do not edit.\n"
         "// ZP*ZP (the box spline with the lattice directions (1,0), (1,1), (0,1), (-1,1) each\n"
-        "// twice), centred: on the mesh triangle T0 = {0 <= dy <= dx, dx + dy <= 1} the weight\n"
-        "// of stencil offset (lx, ly) = (i % 6 - 2, i / 6 - 2) at (dx, dy) is\n"
-        "// sum_r kZp2Coef[i][r] dx^p dy^q, (p, q) = kZp2Mono[r].\n"
+        "// twice), centred: on the mesh triangle T0 = {0 <= dy <= dx, dx + dy <= 1}, with\n"
+        "// u = dx - 1/2, the weights of the stencil offsets (lx, ly) = (i % 3 - 2, i / 3 - 2) and\n"
+        "// (1 - lx, ly) at (dx, dy) are sum_r kZp2Half[i][r] (+-u)^p dy^q / kZp2Den,\n"
+        "// (p, q) = kZp2Mono[r] (+u for the first, -u for the second); the coefficients are\n"
+        "// exact integers.\n"
         "#pragma once\n\nnamespace svf {\n\n"
         f"constexpr int kZp2Deg = {DEG};\n"
+        f"constexpr double kZp2Den = {den}.0;\n"
         "constexpr int kZp2Mono[28][2] = {" + ", ".join(f"{{{p}, {q}}}" for p, q in MONO) + "};\n\n"
-        "constexpr double kZp2Coef[36][28] = {\n" + "\n".join(rows) + "\n};\n\n}  // namespace svf\n")
+        "constexpr double kZp2Half[18][28] = {\n" + "\n".join(rows) + "\n};\n\n}  // namespace svf\n")
     if out is None:
         out = Path(__file__).resolve().parent / "csrc" / "svf_zp2_table.h"
     out.write_text(text)

@@ -126,3 +126,21 @@ def test_single_rejects(ctx):
     e_f = P.svf_field(None, P.SVF_FIELD_SRT3, 0, 15)
     st, rep = P.svf_filter_single(ctx, e_in, e_f, 2, None, e_out, None, report=True)
     assert st == P.SVF_OK and rep.overflow_px == 0
+
+
+def test_single_bench_workload_sampled(ctx):
+    # the benchmark's single-pass workload (2048^2, sigma 3-12, seed 3005) in its launch
+    # configuration, on rectangles at the smallest and the largest filters and at a corner
+    n, seed = 2048, 3005
+    img = I.uniform_image(n, n, seed)
+    fld = I.srt_field(n, n, seed, sigma_range=(3.0, 12.0), rho_range=(1.0, 3.0))
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3)
+    assert rep.overflow_px == 0
+    s = fld[..., 0]
+    lo = np.unravel_index(np.argmin(s[8:-8, 8:-8]), (n - 16, n - 16))
+    hi = np.unravel_index(np.argmax(s[8:-8, 8:-8]), (n - 16, n - 16))
+    rects = [(int(lo[0]) + 4, int(lo[1]) + 4, 8, 8), (int(hi[0]) + 4, int(hi[1]) + 4, 6, 6), (0, n - 8, 8, 8)]
+    for r0, c0, h, w in rects:
+        a, _ = oracle.scales(fld[r0:r0 + h, c0:c0 + w], oracle.FIELD_SRT3, 2)
+        ref = oracle.pass_single(img, a, 2, "brute", r0, c0)
+        assert compare(got[r0:r0 + h, c0:c0 + w], ref, f"2048^2 at {(r0, c0)} sigma {s[r0, c0]:.1f}") == 0

@@ -14,10 +14,20 @@ HDR = Path(__file__).resolve().parents[1] / "paper_1003_2022_amd" / "csrc" / "sv
 
 
 def load():
+    """(monomials, C[36][28]): the coefficients in (u, dy), u = dx - 1/2, of every offset
+    (i % 6 - 2, i / 6 - 2), rebuilt from the mirror pairs the header keeps."""
     src = HDR.read_text()
     mono = [tuple(map(int, m)) for m in re.findall(r"\{(\d), (\d)\}", src.split("kZp2Mono[28][2] =")[1].split(";")[0])]
-    rows = re.findall(r"\{([^{}]*)\},\s*// \((-?\d), (-?\d)\)", src)
-    C = np.array([[float(v) for v in r[0].split(",")] for r in rows])
+    den = float(re.search(r"kZp2Den = ([0-9.]+);", src).group(1))
+    body = src.split("kZp2Half[18][28] = {")[1].split("};")[0]
+    vals = [float(v) for v in re.findall(r"[-+]?\d[\d.eE+-]*", re.sub(r"//[^\n]*", "", body))]
+    half = np.array(vals).reshape(18, 28) / den
+    C = np.zeros((36, 28))
+    sign = np.array([(-1.0) ** p for p, q in mono])
+    for i in range(18):
+        lx, ly = i % 3 - 2, i // 3 - 2
+        C[(ly + 2) * 6 + lx + 2] = half[i]
+        C[(ly + 2) * 6 + (1 - lx) + 2] = half[i] * sign
     return mono, C
 
 
@@ -36,7 +46,7 @@ def weights(mono, C, dx, dy):
     for i in range(36):
         a, b = i % 6 - 2, i // 6 - 2
         l = [(a, b), (1 - b, a), (1 - a, 1 - b), (b, 1 - a)][q]
-        out[l] = sum(c * px ** p * py ** qq for c, (p, qq) in zip(C[i], mono))
+        out[l] = sum(c * (px - 0.5) ** p * py ** qq for c, (p, qq) in zip(C[i], mono))
     return out
 
 
