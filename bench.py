@@ -525,9 +525,9 @@ def single_leg(P, I, ctx, torch, steps=5):
     P.svf_set_timing(ctx, False)
     us = {k: tot / max(n, 1) * 1e3 for k, (tot, n) in kt.items()}
     # FP64 work per pixel: per tap the table contraction (2 flops per non-zero coefficient,
-    # and a sum and a difference per mirror pair of samples), the degree-6 evaluation
-    # (28 FMAs, 12 powers, 28 monomial products) and the tap position (about 10); 81 taps
-    per_tap = 2 * zp2_nonzeros() + 2 * 18 + 2 * 28 + 12 + 28 + 10
+    # and a sum and a difference per mirror pair of samples), the degree-6 polynomial by
+    # Horner's rule (27 FMAs) and the tap position (about 10); 81 taps
+    per_tap = 2 * zp2_nonzeros() + 2 * 18 + 2 * 27 + 10
     flops_px = 81 * per_tap
     achieved = flops_px * SP_N * SP_N / (us["fd"] * 1e-6) / 1e12
     r0, c0, h, w = SP_RECT
