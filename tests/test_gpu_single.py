@@ -144,3 +144,27 @@ def test_single_bench_workload_sampled(ctx):
         a, _ = oracle.scales(fld[r0:r0 + h, c0:c0 + w], oracle.FIELD_SRT3, 2)
         ref = oracle.pass_single(img, a, 2, "brute", r0, c0)
         assert compare(got[r0:r0 + h, c0:c0 + w], ref, f"2048^2 at {(r0, c0)} sigma {s[r0, c0]:.1f}") == 0
+
+
+def test_single_strided_views(ctx):
+    # image, field and output as crops of larger buffers (row_stride > W * C)
+    big = I.uniform_image(40, 50, 8, channels=2)
+    bigf = I.srt_field(40, 50, 8, sigma_range=(2.5, 4.0), rho_range=(1.0, 2.5))
+    r0, c0, h, w = 5, 7, 23, 31
+    img = np.ascontiguousarray(big[r0:r0 + h, c0:c0 + w])
+    fld = np.ascontiguousarray(bigf[r0:r0 + h, c0:c0 + w])
+    x = to_dev(big)[r0:r0 + h, c0:c0 + w]
+    f = to_dev(bigf)[r0:r0 + h, c0:c0 + w]
+    outbig = torch.full((h + 3, w + 9, 2), 5.0, dtype=torch.float32, device=DEV)
+    out = outbig[1:1 + h, 4:4 + w]
+    st, rep = P.svf_filter_single(ctx, P.image_of(x), P.field_of(f, P.SVF_FIELD_SRT3), 2, None, P.image_of(out),
+                                  None, report=True)
+    torch.cuda.synchronize()
+    assert st == P.SVF_OK, ctx.last_error()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.filter_single(img, fld, oracle.FIELD_SRT3, 2)
+    assert compare(got, ref, "strided views") == 0
+    ob = outbig.cpu().numpy()
+    mask = np.ones(ob.shape[:2], bool)
+    mask[1:1 + h, 4:4 + w] = False
+    assert (ob[mask] == 5.0).all(), "wrote outside the output view"
