@@ -20,6 +20,7 @@
 
 #include "svf_device.h"
 #include "svf_internal.h"
+#include "svf_sincos_table.h"
 
 namespace svf {
 
@@ -50,6 +51,15 @@ __device__ __forceinline__ double sqrt_pos(double x)   // x > 0
     g = fma(g, r, g);
     h = fma(h, r, h);
     return fma(fma(-g, g, x), h, g);
+}
+
+// Square root for a value stored in binary32: the hardware estimate and one
+// Goldschmidt step, ~1e-14 relative.
+__device__ __forceinline__ double sqrt_f32out(double x)   // x > 0
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double g = x * y, h = 0.5 * y;
+    return fma(g, fma(-g, h, 0.5), g);
 }
 
 // d/dt of ||K||^2 along p = pbar + t (1,-1,1,-1), where ||K||^2 = sum p^4 + (p1^2+p3^2)(p2^2+p4^2)
@@ -164,16 +174,18 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
         double v = p[k];
         if (v <= eps * (1.0 + 1e-12)) eps_act = true;
         v = fmax(v, eps);
-        a[k] = sqrt_pos(v);
+        a[k] = sqrt_f32out(v);
     }
 }
 
 // sin and cos of th: Cody-Waite reduction modulo pi/2 (pi/2 as the sum of two
-// doubles, the product with the quotient taken by fused multiply-adds) and the
-// Taylor series of sin (to r^17) and cos (to r^16) on |r| <= pi/4, whose
-// truncation error is below 1e-19; about a third of the library routine's cost.
-// Accurate to about one ulp for |th| < 2^20 (field angles lie in [0, pi));
-// beyond that the two-double pi/2 no longer makes the reduction exact.
+// doubles, the product with the quotient taken by fused multiply-adds) to |r| <= pi/4,
+// then r = k h + e with h = pi/128 to 46 significant bits (k h exact, e exact,
+// |e| <= h/2): sin r = sin(kh) cos e + cos(kh) sin e, cos r = cos(kh) cos e - sin(kh) sin e,
+// the pair (sin(kh), cos(kh)) from a 65-entry table (svf_sincos_table.h) and the
+// Taylor series of sin e to e^5 and cos e to e^6 (truncation below 1e-17).  About 2 ulp
+// for |th| < 2^20 (field angles lie in [0, pi)); about half the operations of a
+// series on the whole quarter period.
 __device__ __forceinline__ void sincos_red(double th, double *sn, double *cs)
 {
     constexpr double kTwoOverPi = 0.63661977236758134308;
@@ -181,26 +193,13 @@ __device__ __forceinline__ void sincos_red(double th, double *sn, double *cs)
     constexpr double kPio2Lo = 6.12323399573676603587e-17;   // pi/2 - kPio2Hi
     const double q = rint(th * kTwoOverPi);
     const double r = fma(-q, kPio2Lo, fma(-q, kPio2Hi, th));
-    const double r2 = r * r;
-    // 1/n! for n = 3, 5, ..., 17 and n = 2, 4, ..., 16, with alternating signs
-    double ps = 2.8114572543455206e-15;                 // 1/17!
-    ps = fma(ps, r2, -7.647163731819816e-13);           // -1/15!
-    ps = fma(ps, r2, 1.6059043836821613e-10);           // 1/13!
-    ps = fma(ps, r2, -2.505210838544172e-08);           // -1/11!
-    ps = fma(ps, r2, 2.7557319223985893e-06);           // 1/9!
-    ps = fma(ps, r2, -0.0001984126984126984);           // -1/7!
-    ps = fma(ps, r2, 0.008333333333333333);             // 1/5!
-    ps = fma(ps, r2, -0.16666666666666666);             // -1/3!
-    const double sv = fma(r * r2, ps, r);
-    double pc = 4.779477332387385e-14;                  // 1/16!
-    pc = fma(pc, r2, -1.1470745597729725e-11);          // -1/14!
-    pc = fma(pc, r2, 2.08767569878681e-09);             // 1/12!
-    pc = fma(pc, r2, -2.755731922398589e-07);           // -1/10!
-    pc = fma(pc, r2, 2.48015873015873e-05);             // 1/8!
-    pc = fma(pc, r2, -0.001388888888888889);            // -1/6!
-    pc = fma(pc, r2, 0.041666666666666664);             // 1/4!
-    pc = fma(pc, r2, -0.5);                             // -1/2!
-    const double cv = fma(r2, pc, 1.0);
+    const double k = fmin(fmax(rint(r * kSinCosInvH), -32.0), 32.0);
+    const double e = fma(-k, kSinCosH, r);
+    const double2 t = *reinterpret_cast<const double2 *>(&kSinCosTab[(int)k + 32][0]);
+    const double e2 = e * e;
+    const double se = fma(e * e2, fma(e2, 1.0 / 120.0, -1.0 / 6.0), e);
+    const double ce = fma(e2, fma(e2, fma(e2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double sv = fma(t.x, ce, t.y * se), cv = fma(t.y, ce, -(t.x * se));
     switch ((int)q & 3) {
     case 0: *sn = sv; *cs = cv; break;
     case 1: *sn = cv; *cs = -sv; break;
