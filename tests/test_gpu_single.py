@@ -168,3 +168,19 @@ def test_single_strided_views(ctx):
     mask = np.ones(ob.shape[:2], bool)
     mask[1:1 + h, 4:4 + w] = False
     assert (ob[mask] == 5.0).all(), "wrote outside the output view"
+
+
+def test_single_window_beyond_lds(ctx):
+    # supports whose window exceeds the work-group's LDS: every output of such a tile is
+    # NaN, counted, SVF_ERANGE; a smaller filter elsewhere in the image still runs
+    img = I.uniform_image(40, 72, 9)
+    fld = I.constant_srt_field(40, 72, 40.0)
+    fld[:, :24, 0] = 3.0                      # the left tiles: small filters
+    x = to_dev(img)
+    out = torch.empty(img.shape, dtype=torch.float32, device=DEV)
+    st, rep = P.svf_filter_single(ctx, P.image_of(x), P.field_of(to_dev(fld), P.SVF_FIELD_SRT3), 2,
+                                  P.default_opts(), P.image_of(out), None, report=True)
+    got = out.cpu().numpy()
+    assert st == P.SVF_ERANGE and rep.overflow_px == int(np.isnan(got).sum()) > 0
+    assert np.isnan(got[:, 32:]).all()        # tiles whose pixels all have sigma 40
+    assert rep.max_reach_px > 60
