@@ -218,9 +218,12 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
  * Precision: the doubled sums grow like the window side^8, so the outputs of small
  * filters on busy images lose digits: a pixel whose rounding bound
  * 2^-46 max|g2| / prod_k a_k^2 (max over its tile's window) exceeds 1e-6 of the window's
- * largest input magnitude is written as NaN, as are the pixels of a tile whose window
- * exceeds the 160 KiB of LDS (support half-width about 60 px) and pixels with invalid
- * SVF_FIELD_SCALES4 scales.  With rep != NULL the call waits, fills *rep
+ * largest input magnitude is written as NaN, as are pixels with invalid
+ * SVF_FIELD_SCALES4 scales.  Windows up to the 157 KiB of LDS a work-group takes
+ * (support half-width up to about 60 px) are summed in LDS; larger ones go to a
+ * second launch that keeps each window in a global-memory slot of the context
+ * (512 slots of the largest window: 0.5 GB at a half-width of 170 px; counted against
+ * the context's budget).  With rep != NULL the call waits, fills *rep
  * (overflow_px = NaN outputs, max_reach_px = largest beta^{4,2} support half-width) and
  * returns SVF_ERANGE if some output is NaN, SVF_EINVAL for invalid field entries.  The
  * call waits for the scale map in any case (the window size follows from it).

@@ -391,6 +391,7 @@ svf_status svf_destroy(svf_ctx *ctx)
         if (s) hipStreamDestroy(s);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->lut) hipFree(ctx->lut);
+    if (ctx->slots) hipFree(ctx->slots);
     if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
     delete ctx;
     return SVF_OK;

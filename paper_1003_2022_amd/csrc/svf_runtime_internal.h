@@ -42,6 +42,9 @@ struct svf_ctx {
     float *lut = nullptr;
     int lut_n = 0;
     double lut_eps = 0.0;
+    // svf_filter_single: global-memory window slots for tiles whose window exceeds the LDS
+    void *slots = nullptr;
+    size_t slots_bytes = 0;
 };
 
 namespace svf {

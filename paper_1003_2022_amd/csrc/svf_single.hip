@@ -25,8 +25,9 @@
 //
 // Precision: the doubled sums grow like the window side^8, and the difference cancels
 // all but ~prod a_k^2 of that.  A pixel whose rounding bound 2^-46 max|g2| / prod a_k^2
-// exceeds 1e-6 of the window's largest input magnitude is written as NaN and counted,
-// as are the pixels of a tile whose window does not fit in LDS.  (Measured on the
+// exceeds 1e-6 of the window's largest input magnitude is written as NaN and counted.
+// A tile whose window does not fit in LDS is listed by the first launch and done by a
+// second, persistent one (k_single2_global) with the window in a global-memory slot.  (Measured on the
 // oracle's sums, the error stays below 28 ulp(max|g2|) / prod a_k^2, a quarter of the
 // bound.)
 #include <hip/hip_runtime.h>
@@ -61,6 +62,12 @@ struct SingleJob {
     double inv_sqrt_m;      // 1 / sqrt(2): the pass scales
     int32_t win_cap;        // doubles of dynamic LDS for the window
     uint32_t *nan_count;    // outputs written as NaN
+    // tiles whose window exceeds the LDS: listed (by << 16 | bx, channel) for a second
+    // launch that keeps each window in a global-memory slot (null: NaN instead)
+    uint32_t *defer;
+    uint32_t *defer_count;
+    double *slots;          // one slot per work-group of the second launch
+    int64_t slot_doubles;
 };
 
 // Window layout in the dynamic LDS: rows of stride S (S odd, so that the row scans'
@@ -181,18 +188,20 @@ __device__ __forceinline__ double zp2_interp(const double *g, int base, int dA, 
     return F;
 }
 
+// One output tile (bx, by) of channel ch with its window at g (cap doubles): in LDS
+// (the first launch, defer: a window above cap is listed for the second launch) or
+// in a global-memory slot (the second launch: a window above cap gives NaN).
 template <int IN>
-__global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
+__device__ void single_tile(const SingleJob &J, int bx, int by, int ch, double *g, int64_t cap, bool defer)
 {
-    extern __shared__ double lds[];
     __shared__ int s_box[4];
     __shared__ double s_red[kSpThreads / 64];
     __shared__ double s_part[kSpSplit - 1][kSpT * kSpT];
     __shared__ uint32_t s_nan;
     // thread t: pixel t % 256 of the tile, taps part * kSpTaps .. of it, part = t / 256 (three
     // waves per SIMD with one work-group per CU)
-    const int t = threadIdx.x, ch = blockIdx.z, px_i = t & (kSpT * kSpT - 1), part = t / (kSpT * kSpT);
-    const int64_t r = (int64_t)blockIdx.y * kSpT + px_i / kSpT, c = (int64_t)blockIdx.x * kSpT + px_i % kSpT;
+    const int t = threadIdx.x, px_i = t & (kSpT * kSpT - 1), part = t / (kSpT * kSpT);
+    const int64_t r = (int64_t)by * kSpT + px_i / kSpT, c = (int64_t)bx * kSpT + px_i % kSpT;
     const bool inside = r < J.H && c < J.W;
     if (t == 0) {
         s_box[0] = s_box[2] = INT32_MAX;
@@ -232,7 +241,15 @@ __global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
     const int wc0 = s_box[0], wr0 = s_box[2];
     const int ww = s_box[1] - wc0 + 1, wh = s_box[3] - wr0 + 1;
     const int S = ww | 1;
-    if ((int64_t)wh * S > J.win_cap) {
+    if ((int64_t)wh * S > cap) {
+        if (defer) {
+            if (t == 0) {
+                const uint32_t k = atomicAdd(J.defer_count, 1u);
+                J.defer[2 * k] = ((uint32_t)by << 16) | (uint32_t)bx;
+                J.defer[2 * k + 1] = (uint32_t)ch;
+            }
+            return;
+        }
         if (inside && part == 0) {
             *outp = NAN;
             atomicAdd(&s_nan, 1u);
@@ -241,7 +258,6 @@ __global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
         if (t == 0 && s_nan) atomicAdd(J.nan_count, s_nan);
         return;
     }
-    double *g = lds;
     double fmax_loc = 0.0;
     for (int i = t; i < wh * ww; i += blockDim.x) {
         const int rr = i / ww, cc = i - rr * ww;
@@ -296,6 +312,27 @@ __global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
     if (!run) atomicAdd(J.nan_count, 1u);
 }
 
+template <int IN>
+__global__ __launch_bounds__(kSpThreads) void k_single2(SingleJob J)
+{
+    extern __shared__ double lds[];
+    single_tile<IN>(J, blockIdx.x, blockIdx.y, blockIdx.z, lds, J.win_cap, J.defer != nullptr);
+}
+
+// The listed tiles, a persistent grid: work-group b takes list entries b, b + grid, ...
+// with its own global-memory slot for the window.
+template <int IN>
+__global__ __launch_bounds__(kSpThreads) void k_single2_global(SingleJob J)
+{
+    const uint32_t n = *J.defer_count;
+    double *slot = J.slots + (int64_t)blockIdx.x * J.slot_doubles;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const uint32_t id = J.defer[2 * i], ch = J.defer[2 * i + 1];
+        single_tile<IN>(J, (int)(id & 0xffffu), (int)(id >> 16), (int)ch, slot, J.slot_doubles, false);
+        __syncthreads();   // the shared records and the slot are reused by the next tile
+    }
+}
+
 }  // namespace
 
 }  // namespace svf
@@ -320,9 +357,12 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
     if (rep) std::memset(rep, 0, sizeof *rep);
     if (in->H == 0 || in->W == 0) return SVF_OK;
     // workspace: the scale map's tile records and scales (as for svf_filter), then the
-    // NaN counter
+    // NaN and list counters and the list of tiles for the global-memory launch
     Plan p = plan_for(in, m, &o);
-    const size_t off_cnt = p.off_fdplan, bytes = off_cnt + 256;
+    const int64_t ntx = (in->W + kSpT - 1) / kSpT, nty = (in->H + kSpT - 1) / kSpT;
+    const size_t n_list = (size_t)(ntx * nty * in->channels);
+    const size_t off_cnt = p.off_fdplan, off_list = off_cnt + 256;
+    const size_t bytes = off_list + ((n_list * 8 + 255) / 256) * 256;
     st = ensure_workspace(ctx, bytes);
     if (st) return st;
     const size_t nt = (size_t)p.ntr * p.ntc;
@@ -364,6 +404,31 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
     sj.inv_sqrt_m = 1.0 / std::sqrt(2.0);
     sj.win_cap = win_cap;
     sj.nan_count = reinterpret_cast<uint32_t *>(ws + off_cnt);
+    sj.defer = nullptr;
+    sj.defer_count = reinterpret_cast<uint32_t *>(ws + off_cnt + 4);
+    sj.slots = nullptr;
+    sj.slot_doubles = need;
+    // windows above the LDS: a second, persistent launch with one global-memory slot of
+    // the largest window per work-group
+    const int n_slots = (int)std::min<int64_t>((int64_t)n_list, 512);
+    if (need > cap) {
+        const size_t sb = (size_t)n_slots * (size_t)need * 8;
+        if (ctx->budget && sb > ctx->budget)
+            return fail(ctx, SVF_ENOMEM, "window slots of %zu bytes exceed the HBM budget", sb);
+        if (sb > ctx->slots_bytes) {
+            if (ctx->slots) hipFree(ctx->slots);
+            ctx->slots = nullptr;
+            ctx->slots_bytes = 0;
+            e = hipMalloc(&ctx->slots, sb);
+            if (e != hipSuccess) {
+                ctx->slots = nullptr;
+                return fail(ctx, SVF_ENOMEM, "hipMalloc(%zu) for window slots: %s", sb, hipGetErrorString(e));
+            }
+            ctx->slots_bytes = sb;
+        }
+        sj.defer = reinterpret_cast<uint32_t *>(ws + off_list);
+        sj.slots = static_cast<double *>(ctx->slots);
+    }
     const dim3 grid((unsigned)((in->W + kSpT - 1) / kSpT), (unsigned)((in->H + kSpT - 1) / kSpT),
                     (unsigned)in->channels);
     const size_t lds = (size_t)win_cap * 8;
@@ -372,10 +437,12 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInU16>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(k_single2<kInU16>, grid, dim3(kSpThreads), lds, stream, sj);
+            if (sj.defer) hipLaunchKernelGGL(k_single2_global<kInU16>, dim3(n_slots), dim3(kSpThreads), 0, stream, sj);
         } else {
             hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInF32>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(k_single2<kInF32>, grid, dim3(kSpThreads), lds, stream, sj);
+            if (sj.defer) hipLaunchKernelGGL(k_single2_global<kInF32>, dim3(n_slots), dim3(kSpThreads), 0, stream, sj);
         }
         return hipGetLastError();
     });

@@ -171,16 +171,25 @@ def test_single_strided_views(ctx):
 
 
 def test_single_window_beyond_lds(ctx):
-    # supports whose window exceeds the work-group's LDS: every output of such a tile is
-    # NaN, counted, SVF_ERANGE; a smaller filter elsewhere in the image still runs
-    img = I.uniform_image(40, 72, 9)
-    fld = I.constant_srt_field(40, 72, 40.0)
-    fld[:, :24, 0] = 3.0                      # the left tiles: small filters
-    x = to_dev(img)
-    out = torch.empty(img.shape, dtype=torch.float32, device=DEV)
-    st, rep = P.svf_filter_single(ctx, P.image_of(x), P.field_of(to_dev(fld), P.SVF_FIELD_SRT3), 2,
-                                  P.default_opts(), P.image_of(out), None, report=True)
-    got = out.cpu().numpy()
-    assert st == P.SVF_ERANGE and rep.overflow_px == int(np.isnan(got).sum()) > 0
-    assert np.isnan(got[:, 32:]).all()        # tiles whose pixels all have sigma 40
-    assert rep.max_reach_px > 60
+    # supports whose window exceeds the work-group's LDS go to the second launch (window
+    # in a global-memory slot): same results as the oracle's direct sum
+    img = I.uniform_image(48, 64, 9)
+    fld = I.constant_srt_field(48, 64, 15.0, rho=1.5, theta=0.4)
+    fld[:, :24, 0] = 3.0                      # left tiles: small filters (LDS windows)
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3)
+    assert rep.overflow_px == 0 and rep.max_reach_px > 60
+    a, _ = oracle.scales(fld, oracle.FIELD_SRT3, 2)
+    for r0, c0 in [(20, 4), (22, 40), (0, 60)]:
+        ref = oracle.pass_single(img, a[r0:r0 + 3, c0:c0 + 3], 2, "brute", r0, c0)
+        assert compare(got[r0:r0 + 3, c0:c0 + 3], ref, f"beyond LDS at {(r0, c0)}") == 0
+
+
+def test_single_very_large_filters(ctx):
+    # sigma 40 (support half-width ~170 px, 1 MB windows): a constant image stays constant
+    # far from the borders (the sampled mass of beta^{4,2} at these scales is 1 to ~1e-9)
+    img = np.ones((600, 600), dtype=np.float32)
+    fld = I.constant_srt_field(600, 600, 40.0)
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3)
+    assert rep.overflow_px == 0
+    c = got[250:350, 250:350]
+    assert np.abs(c - 1.0).max() < 1e-6, np.abs(c - 1.0).max()
