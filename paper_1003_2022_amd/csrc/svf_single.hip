@@ -25,17 +25,17 @@
 //
 // Precision: the doubled sums grow like the window side^8, and the difference cancels
 // all but ~prod a_k^2 of that.  A pixel whose rounding bound 2^-46 max|g2| / prod a_k^2
-// exceeds 1e-6 of the window's largest input magnitude is written as NaN and counted.
+// exceeds 1e-6 of the window's largest input magnitude is written as NaN and counted
+// (measured on the oracle's sums, the error stays below 28 ulp(max|g2|) / prod a_k^2,
+// a quarter of the bound).
+//
 // A tile whose window does not fit in LDS is listed by the first launch and done by a
-// second, persistent one (k_single2_global) with the window in a global-memory slot.  (Measured on the
-// oracle's sums, the error stays below 28 ulp(max|g2|) / prod a_k^2, a quarter of the
-// bound.)
+// second, persistent one (k_single2_global) with the window in a global-memory slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <vector>
 
 #include "svf_internal.h"
 #include "svf_runtime_internal.h"
