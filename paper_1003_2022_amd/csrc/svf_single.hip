@@ -70,8 +70,8 @@ struct SingleJob {
     int64_t slot_doubles;
 };
 
-// Window layout in the dynamic LDS: rows of stride S (S odd, so that the row scans'
-// lanes spread over the banks).
+// Window layout (in LDS, or in a global-memory slot): rows of stride S (S odd, so that
+// the row scans' lanes spread over the LDS banks).
 
 template <int IN>
 __device__ __forceinline__ double in_at(const SingleJob &J, int64_t r, int64_t c, int ch)
@@ -98,9 +98,9 @@ __device__ __forceinline__ double block_max(double v, double *red)
     return m;
 }
 
-// One recursion along one line of the window, in place: p[k step] += mul * (running sum)
-// (RS1 / RS3: mul = 1, exact; RS2 / RS4: sqrt2).  Eight loads are issued before their
-// sums, so the line's LDS latency is paid once per eight samples.
+// One recursion along one line of the window, in place: p[k step] becomes
+// sum_{i <= k} mul p[i step] (RS1 / RS3: mul = 1, exact; RS2 / RS4: sqrt2).  Eight loads
+// are issued before their sums, so the line's latency is paid once per eight samples.
 __device__ __forceinline__ void scan_line(double *p, int step, int len, double mul)
 {
     double s = 0.0;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void scan_line(double *p, int step, int len, double m
     }
 }
 
-// One application of RS1..RS4 to the window in LDS, in place, each recursion over the
+// One application of RS1..RS4 to the window, in place, each recursion over the
 // whole window before the next: RS1 along the rows, RS2 down the diagonals (step
 // (1,1)), RS3 down the columns, RS4 down the anti-diagonals (step (-1,1)), every line a
 // thread of its own (zero initial conditions at the window's top, left and right edges).
