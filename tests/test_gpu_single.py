@@ -193,3 +193,28 @@ def test_single_very_large_filters(ctx):
     assert rep.overflow_px == 0
     c = got[250:350, 250:350]
     assert np.abs(c - 1.0).max() < 1e-6, np.abs(c - 1.0).max()
+
+
+def test_single_lut_scale_map(ctx):
+    # the look-up-table scale map feeds the single pass as it feeds svf_filter
+    img = I.uniform_image(30, 34, 10)
+    fld = I.srt_field(30, 34, 10, sigma_range=(2.5, 4.0), rho_range=(1.0, 3.0))
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3, scale_map=P.SVF_SCALE_LUT)
+    a = oracle.scales_lut(fld, oracle.FIELD_SRT3, 2)
+    ref = oracle.pass_single(img, a, 2, "brute")
+    assert compare(got, ref, "lut scale map") == 0
+
+
+def test_single_invalid_scales(ctx):
+    # SVF_FIELD_SCALES4 entries that are not finite and positive give NaN there and EINVAL
+    img = I.uniform_image(20, 20, 11)
+    fld = I.scales_field(20, 20, 11, lo=4.0, hi=6.0, smooth=True)
+    fld[5, 7] = [-1.0, 4.0, 4.0, 4.0]
+    fld[12, 3, 2] = np.nan
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SCALES4, expect=P.SVF_EINVAL)
+    assert np.isnan(got[5, 7]) and np.isnan(got[12, 3])
+    assert rep.invalid_px == 2 and int(np.isnan(got).sum()) == 2
+    ok = np.ones(got.shape, bool)
+    ok[5, 7] = ok[12, 3] = False
+    ref = oracle.pass_single(img, np.where(ok[..., None], fld, 5.0) / np.sqrt(2.0), 2, "brute")
+    assert compare(np.where(ok, got, ref), ref, "valid pixels beside invalid scales") == 0
