@@ -101,12 +101,13 @@ __device__ __forceinline__ Cubic zeta_cubic(const double *pb)
 // Its root t: Cardano's formula with the larger cube root taken first (the two
 // terms of u have one sign, so nothing cancels), at the hardware estimates' ~1e-7
 // and a binary32 cube root, x0 within ~1e-6 of the scale; two Newton steps on the
-// depressed cubic (error e -> K e^2 + 1e-7 e, K <= 0.9 / sqrt(P)), which as written
-// resolve the root only to ~1e-11 of the scale where P is small (P, Q come from
-// cancelling sums); and a last Newton step on zeta' evaluated from the shifted
-// components (kurt_d), accurate to ~1e-16 of the scale.  `last` is that step, for
-// the caller's convergence check.
-__device__ __forceinline__ double cubic_root(const double *pb, const Cubic &c, double &last)
+// depressed cubic (error e -> K e^2 + 1e-7 e, K <= 0.9 / sqrt(P)).  As written they
+// resolve the root to ~3e-14 of the scale where P >= scale^2 / 100 (checked against
+// exact rational roots; enough for scales stored in binary32) but only to ~1e-11 where
+// P is smaller (P, Q come from cancelling sums); there a last Newton step on zeta'
+// evaluated from the shifted components (kurt_d) takes it to ~1e-16.  `last` is the
+// last step taken, for the caller's convergence check.
+__device__ __forceinline__ double cubic_root(const double *pb, const Cubic &c, double scale, double &last)
 {
     const double D = 0.25 * c.Q * c.Q + c.P * c.P * c.P * (1.0 / 27.0);   // > 0
     const double sD = D > 0.0 ? D * __builtin_amdgcn_rsq(D) : 0.0;
@@ -118,13 +119,17 @@ __device__ __forceinline__ double cubic_root(const double *pb, const Cubic &c, d
     for (int k = 0; k < 2; ++k) {
         const double x2 = x * x;
         const double f = fma(x, x2 + c.P, c.Q), fp = fma(3.0, x2, c.P);
-        x -= f * __builtin_amdgcn_rcp(fp);
+        last = f * __builtin_amdgcn_rcp(fp);
+        x -= last;
     }
-    const double t = x - c.b;
-    double d1, d2;
-    kurt_d(pb, t, d1, d2);
-    last = d1 * __builtin_amdgcn_rcp(d2);
-    return t - last;
+    double t = x - c.b;
+    if (!(c.P >= 0.01 * scale * scale)) {
+        double d1, d2;
+        kurt_d(pb, t, d1, d2);
+        last = d1 * __builtin_amdgcn_rcp(d2);
+        t -= last;
+    }
+    return t;
 }
 
 // Covariance (whole filter) -> scales, floor eps on a^2.  The feasible set of
@@ -147,7 +152,7 @@ __device__ void solve_feasible(double C11, double C12, double C22, double eps, d
     const double scale = fmax(fmax(fabs(pb[0]), fabs(pb[1])), fmax(fabs(pb[2]), 1.0));
     const Cubic cb = zeta_cubic(pb);
     double last;
-    double t = cubic_root(pb, cb, last);
+    double t = cubic_root(pb, cb, scale, last);
     if (fabs(last) <= 1e-9 * scale) {
         t = fmin(fmax(t, lo), hi);
     } else {
