@@ -226,8 +226,10 @@ svf_status svf_filter(svf_ctx *ctx, const svf_image *in, const svf_field *field,
  * the context's budget).  With rep != NULL the call waits, fills *rep
  * (overflow_px = NaN outputs, max_reach_px = largest beta^{4,2} support half-width) and
  * returns SVF_ERANGE if some output is NaN, SVF_EINVAL for invalid field entries.  The
- * call waits for the scale map in any case (the window size follows from it).
- * SVF_EUNSUPPORTED: m != 2, opts.boundary other than zero, opts.preint other than
+ * call waits for the scale map in any case (the window size follows from it).  A
+ * support half-width above 2 opts.max_reach_px (two passes' worth) returns SVF_ERANGE
+ * after the scale map, with the output not written (the report, if asked for, holds
+ * the counts and max_reach_px).  SVF_EUNSUPPORTED: m != 2, opts.boundary other than zero, opts.preint other than
  * SVF_PRE_F64, opts.fd_fp32, opts.bands > 1.  out must not alias in.
  */
 svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const svf_field *field, int m,

@@ -384,8 +384,18 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
     if (e != hipSuccess) return hip_fail(ctx, e, "tile records");
     float mx = 0.f;
     for (size_t i = 0; i < nt; ++i) mx = std::max(mx, std::max(hts[i].rx, hts[i].ry));
-    // support half-width of beta^{4,2} with the pass scales a / sqrt2: 2 rx / sqrt2
+    // support half-width of beta^{4,2} with the pass scales a / sqrt2: 2 rx / sqrt2, at
+    // most that of two passes of beta^4 within max_reach_px (windows, slots and their
+    // 32-bit indexes stay bounded); beyond it nothing more is enqueued
     const double reach = std::sqrt(2.0) * mx;
+    if (!(reach <= 2.0 * o.max_reach_px)) {
+        if (rep) {
+            fill_report(hts, nt, m, rep);
+            rep->max_reach_px = reach;
+        }
+        return fail(ctx, SVF_ERANGE, "single pass: support half-width %.1f px above 2 max_reach_px = %d (output not written)",
+                    reach, 2 * o.max_reach_px);
+    }
     const int side = kSpT + 2 * ((int)std::ceil(reach) + 6);
     const int64_t need = (int64_t)side * (side | 1);
     const int cap = kSpLdsBytes / 8;
@@ -416,7 +426,11 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
         if (ctx->budget && sb > ctx->budget)
             return fail(ctx, SVF_ENOMEM, "window slots of %zu bytes exceed the HBM budget", sb);
         if (sb > ctx->slots_bytes) {
-            if (ctx->slots) hipFree(ctx->slots);
+            if (ctx->slots) {   // a previous call's launch may still read the slots
+                e = hipDeviceSynchronize();
+                if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+                hipFree(ctx->slots);
+            }
             ctx->slots = nullptr;
             ctx->slots_bytes = 0;
             e = hipMalloc(&ctx->slots, sb);

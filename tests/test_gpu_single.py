@@ -218,3 +218,15 @@ def test_single_invalid_scales(ctx):
     ok[5, 7] = ok[12, 3] = False
     ref = oracle.pass_single(img, np.where(ok[..., None], fld, 5.0) / np.sqrt(2.0), 2, "brute")
     assert compare(np.where(ok, got, ref), ref, "valid pixels beside invalid scales") == 0
+
+
+def test_single_support_beyond_bound(ctx):
+    # a support half-width above 2 max_reach_px: SVF_ERANGE after the scale map, output untouched
+    img = I.uniform_image(24, 24, 12)
+    fld = I.constant_srt_field(24, 24, 6.0)
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3, expect=P.SVF_ERANGE, max_reach_px=4)
+    assert rep.max_reach_px > 8.0
+    assert np.all(got == 7.0)
+    # the same field within the bound is filtered
+    got, rep = run(ctx, img, fld, P.SVF_FIELD_SRT3, max_reach_px=16)
+    assert 8.0 < rep.max_reach_px <= 32.0 and np.isfinite(got).all()
