@@ -416,6 +416,17 @@ def table2_leg(P, I, ctx, torch, steps=20):
             ms = (time.perf_counter() - t) * 1e3 / steps
             row = {"image": n, "sigma": sigma, "s_px2": 2 * sigma * sigma, "ms_per_filter": round(ms, 4),
                    "Mpixel_s": round(n * n / (ms * 1e-3) / 1e6, 1)}
+            # which kernel grows with the filter size (event times, separate calls)
+            P.svf_set_timing(ctx, True)
+            for k in ("scale_map", "preint", "fd"):
+                P.svf_kernel_time(ctx, k, reset=True)
+            for _ in range(5):
+                P.svf_filter(ctx, im_d, fl_d, 4, 1, o, o_d, stream)
+            torch.cuda.synchronize()
+            row["kernel_avg_us"] = {k: round(tot / max(cnt, 1) * 1e3, 2)
+                                    for k, (tot, cnt) in ((k, P.svf_kernel_time(ctx, k))
+                                                          for k in ("scale_map", "preint", "fd"))}
+            P.svf_set_timing(ctx, False)
             if n == 512:   # one call from the host to the finished result
                 lat = []
                 for _ in range(10):
@@ -426,7 +437,8 @@ def table2_leg(P, I, ctx, torch, steps=20):
                 row["sync_call_ms_median"] = round(float(np.median(lat)), 4)
             res["rows"].append(row)
             log(f"table2 {n}^2 sigma {sigma}: {ms:.3f} ms/filter ({row['Mpixel_s']} Mpx/s)"
-                + (f", synchronous call {row['sync_call_ms_median']:.3f} ms" if n == 512 else ""))
+                + (f", synchronous call {row['sync_call_ms_median']:.3f} ms" if n == 512 else "")
+                + "; kernels " + " ".join(f"{k} {v:.1f} us" for k, v in row["kernel_avg_us"].items()))
     return res
 
 
