@@ -14,6 +14,40 @@ constexpr double kRsqrt2 = 0.70710678118654752440;
 constexpr int kBufWord3 = 0x00020000;   // buffer resource word 3 for gfx9-family raw loads
 
 // ---------------------------------------------------------------------------
+// A descriptor read from a device table (batched launches) as wave-uniform values.
+// The table is ordinary read-write memory, so the compiler reads it with vector
+// loads and would treat everything derived from it (buffer resources above all)
+// as varying per lane: each buffer access would then be wrapped in a loop over the
+// distinct lane values.  One readfirstlane per dword restores the scalar form that
+// a descriptor passed as a kernel argument has.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ S uniform_copy(const S *p)
+{
+    static_assert(sizeof(S) % 4 == 0, "whole dwords");
+    S v;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return v;
+}
+
+// A load through a pointer read from a device table, as a global load: the
+// compiler cannot tell what such a pointer addresses and would issue a flat load,
+// which also counts against the LDS wait counter (so every LDS barrier would wait
+// for it).  Pointers that arrive as kernel arguments are known global already.
+template <class T>
+__device__ __forceinline__ T load_global(const T *p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(1))) T *)p;
+#else
+    return *p;
+#endif
+}
+
+// ---------------------------------------------------------------------------
 // LDS-only work-group barrier: orders LDS accesses without waiting for global
 // loads in flight, so the row sweep keeps its input prefetches across barriers.
 // ---------------------------------------------------------------------------

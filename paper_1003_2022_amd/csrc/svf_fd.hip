@@ -397,7 +397,7 @@ __device__ __forceinline__ void fd_block(const Job &J, int gb, double (*lds)[NCH
     constexpr int PF = fd_prefetch<NCH>();
     constexpr int NB = fd_buffers<PRE, NCH>();
     constexpr bool kDirect = PRE == kPreF64;   // loads write the regions in LDS themselves
-    const FdBlk &B = J.fdplan[gb];
+    const FdBlk B = uniform_copy(J.fdplan + gb);
     const int64_t br0 = B.br0, bc0 = B.bc0;
     if (br0 >= J.H || bc0 >= J.W) return;   // uniform: block entirely outside a ragged tile
     const int tile = B.tile;
@@ -561,7 +561,7 @@ __device__ __forceinline__ void fd_block(const Job &J, int gb, double (*lds)[NCH
 
 // binary64 windows: 5 waves per SIMD for one channel, 4 for several (measured at
 // 4096^2 with 3 channels: 4 waves, with a 36-byte spill, 3-4 % faster than the 3 the
-// compiler picks by itself)
+// compiler picks by itself); the batched kernel below takes the same setting
 template <int PRE, int NCH, typename R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPreF64 && NCH == 1 ? 5 : (PRE == kPreF64 ? 4 : 1), 8))) void k_fd(Job J, int nblocks)
 {
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPre
 // block list (eighths of the work list itself, not of the grid: a rounded-up grid
 // would otherwise leave the last XCDs without work).
 template <int PRE, int NCH, typename R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPreF64 && NCH == 1 ? 5 : 1, 8))) void k_fd_batch(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPreF64 && NCH == 1 ? 5 : (PRE == kPreF64 ? 4 : 1), 8))) void k_fd_batch(
     const Job *jobs, int n, int total, const BatchDims *dims)
 {
     __shared__ double lds[fd_buffers<PRE, NCH>()][NCH][kRegPad];
@@ -590,9 +590,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE == kPre
     const int b = (blockIdx.x & 7) * per + slot;
     if (slot >= per || b >= total) return;
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 1));
-    // a copy in registers: read from the table in memory, the descriptor would be
-    // read again after every load into LDS (which may write any memory)
-    const Job J = jobs[j];
+    // a wave-uniform copy in registers: read from the table in memory, the descriptor
+    // would be read again after every load into LDS (which may write any memory)
+    const Job J = uniform_copy(jobs + j);
     fd_block<PRE, NCH, R>(J, b - J.blk_base, lds);
 }
 

@@ -505,7 +505,7 @@ __global__ __launch_bounds__(256) void k_scale_map_batch(const Job *jobs, int n,
     }
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
-        const Job &J = jobs[j];
+        const Job J = uniform_copy(jobs + j);
         scale_map_block<false, KIND>(J, b - J.smap_base);
     }
 }
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) void k_scale_map_batch_lut(const Job *jobs, in
     }
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 2));
-        const Job &J = jobs[j];
+        const Job J = uniform_copy(jobs + j);
         scale_map_block<true>(J, b - J.smap_base);
     }
 }
@@ -528,7 +528,7 @@ __global__ void k_fill_jobs(const Job *jobs, int n, const BatchDims *dims)
 {
     if (dims) n = dims->n;
     for (int j = blockIdx.x; j < n; j += gridDim.x) {
-        const Job &J = jobs[j];
+        const Job J = uniform_copy(jobs + j);
         uint32_t *t = reinterpret_cast<uint32_t *>(J.tstat);
         const int64_t words = (int64_t)J.ntr * J.ntc * (int64_t)(sizeof(TileStat) / 4);
         for (int64_t i = threadIdx.x; i < words; i += blockDim.x) t[i] = 0u;
@@ -887,7 +887,7 @@ __device__ __forceinline__ void preint_loader(const Job &J, int ch, const Window
             }
         } else {
 #pragma unroll
-            for (int v = 0; v < P; ++v) dst[v] = rowp[coff[v]];
+            for (int v = 0; v < P; ++v) dst[v] = load_global(rowp + coff[v]);
         }
     };
 #pragma unroll
@@ -1074,10 +1074,11 @@ __global__ __launch_bounds__(64 * kPreWaves) void k_preint_batch(const Job *jobs
     }
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n, b, 0));
-        const Job &J = jobs[j];
+        const Job J = uniform_copy(jobs + j);
         const int lt = b - J.tile_base;
         const int tile = lt / J.C, ch = lt - tile * J.C;
-        const Window w = window_of(J, tile);
+        const Window wl = window_of(J, tile);
+        const Window w = uniform_copy(&wl);   // the tile record is read with vector loads
         void *gout = static_cast<unsigned char *>(J.g) + ((int64_t)tile * J.C + ch) * J.slot_elems * sizeof(typename A::T);
         if (J.in_type == kInU16) preint_window<A, kInU16>(J, ch, w, gout, lds);
         else preint_window<A, kInF32>(J, ch, w, gout, lds);
