@@ -33,10 +33,14 @@ __device__ __forceinline__ S uniform_copy(const S *p)
     return v;
 }
 
-// A load through a pointer read from a device table, as a global load: the
+// A load (store) through a pointer read from a device table, as a global one: the
 // compiler cannot tell what such a pointer addresses and would issue a flat load,
 // which also counts against the LDS wait counter (so every LDS barrier would wait
 // for it).  Pointers that arrive as kernel arguments are known global already.
+// four floats as a native vector: loads and stores of it are single accesses (the
+// HIP float4 class would go through its member operators and a generic pointer)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <class T>
 __device__ __forceinline__ T load_global(const T *p)
 {
@@ -44,6 +48,16 @@ __device__ __forceinline__ T load_global(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 #else
     return *p;
+#endif
+}
+
+template <class T>
+__device__ __forceinline__ void store_global(T *p, const T &v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    *(__attribute__((address_space(1))) T *)p = v;
+#else
+    *p = v;
 #endif
 }
 

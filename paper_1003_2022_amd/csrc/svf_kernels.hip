@@ -379,7 +379,12 @@ __device__ void scale_map_block(const Job &J, int lb)
 #pragma unroll
             for (int k = 0; k < kSmapRows; ++k) {
                 const int64_t r = (int64_t)by * rows_per_block + wave * kSmapRows + k;
-                if (r < J.H && c < J.W) pf[k] = *reinterpret_cast<const FieldEntry *>(J.field + r * J.f_rs + c * 3);
+                if (r < J.H && c < J.W) {
+                    const float *q = J.field + r * J.f_rs + c * 3;   // three adjacent dwords: one access
+                    pf[k].x = load_global(q);
+                    pf[k].y = load_global(q + 1);
+                    pf[k].z = load_global(q + 2);
+                }
             }
         }
     }
@@ -390,7 +395,7 @@ __device__ void scale_map_block(const Job &J, int lb)
         bool cl = false, ea = false, bad = false;
         const float *fv = J.field + r * J.f_rs;
         if (f_kind == kScales4) {
-            const float4 v = *reinterpret_cast<const float4 *>(fv + c * 4);
+            const f32x4 v = load_global(reinterpret_cast<const f32x4 *>(fv + c * 4));
             a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
             bad = !(a[0] > 0.0 && a[1] > 0.0 && a[2] > 0.0 && a[3] > 0.0 && isfinite(a[0] + a[1] + a[2] + a[3]));
         } else {
@@ -398,7 +403,7 @@ __device__ void scale_map_block(const Job &J, int lb)
             if constexpr (kPre) {
                 f0 = pf[k].x; f1 = pf[k].y; f2 = pf[k].z;
             } else {
-                f0 = fv[c * 3]; f1 = fv[c * 3 + 1]; f2 = fv[c * 3 + 2];
+                f0 = load_global(fv + c * 3); f1 = load_global(fv + c * 3 + 1); f2 = load_global(fv + c * 3 + 2);
             }
             if (f_kind == kSrt3) {
                 bad = !(isfinite(f0) && isfinite(f1) && isfinite(f2) && f0 > 0.f && f1 >= 1.f);
@@ -420,7 +425,7 @@ __device__ void scale_map_block(const Job &J, int lb)
             }
             float4 o;
             o.x = (float)a[0]; o.y = (float)a[1]; o.z = (float)a[2]; o.w = (float)a[3];
-            *reinterpret_cast<float4 *>(const_cast<float *>(J.scales) + r * J.sc_rs + c * 4) = o;
+            store_global(reinterpret_cast<f32x4 *>(const_cast<float *>(J.scales) + r * J.sc_rs + c * 4), f32x4{o.x, o.y, o.z, o.w});
             // the windows are sized from the stored (rounded) scales
             a[0] = o.x; a[1] = o.y; a[2] = o.z; a[3] = o.w;
         }
