@@ -368,7 +368,8 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
     const size_t nt = (size_t)p.ntr * p.ntc;
     st = ensure_pinned(ctx, nt * sizeof(TileStat) + 64);
     if (st) return st;
-    hipSetDevice(ctx->device);
+    const hipError_t de = hipSetDevice(ctx->device);
+    if (de != hipSuccess) return hip_fail(ctx, de, "hipSetDevice");
     unsigned char *ws = static_cast<unsigned char *>(ctx->ws);
     Job j = base_job(in, field, m, &o, p, ws);
     st = attach_lut(ctx, o, j, stream);
@@ -448,13 +449,15 @@ extern "C" svf_status svf_filter_single(svf_ctx *ctx, const svf_image *in, const
     const size_t lds = (size_t)win_cap * 8;
     e = timed_launch(ctx, kClsFd, stream, [&] {
         if (sj.in_type == kInU16) {
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInU16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const hipError_t ae = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInU16>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (ae != hipSuccess) return ae;
             hipLaunchKernelGGL(k_single2<kInU16>, grid, dim3(kSpThreads), lds, stream, sj);
             if (sj.defer) hipLaunchKernelGGL(k_single2_global<kInU16>, dim3(n_slots), dim3(kSpThreads), 0, stream, sj);
         } else {
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInF32>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const hipError_t ae = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_single2<kInF32>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (ae != hipSuccess) return ae;
             hipLaunchKernelGGL(k_single2<kInF32>, grid, dim3(kSpThreads), lds, stream, sj);
             if (sj.defer) hipLaunchKernelGGL(k_single2_global<kInF32>, dim3(n_slots), dim3(kSpThreads), 0, stream, sj);
         }
