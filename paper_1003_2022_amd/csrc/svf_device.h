@@ -25,11 +25,12 @@ template <class S>
 __device__ __forceinline__ S uniform_copy(const S *p)
 {
     static_assert(sizeof(S) % 4 == 0, "whole dwords");
-    S v;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+    uint32_t w[sizeof(S) / 4];
+    __builtin_memcpy(w, p, sizeof(S));
 #pragma unroll
-    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    S v;
+    __builtin_memcpy(&v, w, sizeof(S));
     return v;
 }
 

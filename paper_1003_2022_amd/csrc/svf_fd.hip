@@ -226,7 +226,7 @@ struct PixScales {
     bool bad;
     __device__ __forceinline__ PixScales(const Job &J, int64_t r, int64_t c)
     {
-        const float4 af = *reinterpret_cast<const float4 *>(J.scales + r * J.sc_rs + c * 4);
+        const f32x4 af = load_global(reinterpret_cast<const f32x4 *>(J.scales + r * J.sc_rs + c * 4));
         const double d = ((double)af.y + (double)af.w) * kRsqrt2;
         const float px = (float)(0.5 * ((double)af.x + d)) * 1.000001f;
         const float py = (float)(0.5 * ((double)af.z + d)) * 1.000001f;
@@ -330,7 +330,7 @@ __device__ void fd_plan_block(const Job &J, int gb)
     B.ww = w.w;
     B.wh = w.h;
     const int64_t ra = min((int64_t)B.br0 + kFdSide / 2, J.H - 1), ca = min((int64_t)B.bc0 + kFdSide / 2, J.W - 1);
-    const float4 af = *reinterpret_cast<const float4 *>(J.scales + ra * J.sc_rs + ca * 4);
+    const f32x4 af = load_global(reinterpret_cast<const f32x4 *>(J.scales + ra * J.sc_rs + ca * 4));
     const double m = J.inv_sqrt_m_d;
     const double a1 = (double)af.x * m, a3 = (double)af.z * m;
     const double ap2 = (double)af.y * m * kRsqrt2, ap4 = (double)af.w * m * kRsqrt2;
